@@ -1,0 +1,232 @@
+/*
+ * bz.h - C ABI of the MI355X fast spectral Boltzmann collision library.
+ *
+ * The library evaluates, for every spatial cell handed to it, the fast
+ * spectral approximation of the 3D-velocity Boltzmann collision operator
+ * Q(f,f) (Sec. 4.4.1: truncated Carleman operator Q^R, decoupled kernel,
+ * sum over A sphere directions of discrete convolutions evaluated by FFT),
+ * and the moment-realizability regime mask that selects those cells
+ * (Sec. 3.2-3.3 and 4.5, Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: bz_status, 0 = BZ_OK, > 0 = BZ_AGAIN (not ready yet, or no
+ *     room yet), < 0 = error.  No C++ exception crosses the ABI.  The text of
+ *     the last error of the calling thread is returned by bz_last_error().
+ *   - Device pointers are owned by the caller (e.g. torch tensors).  The
+ *     library never allocates device memory: it reports the sizes it needs and
+ *     the caller passes buffers.  Streams are hipStream_t passed as void*
+ *     (NULL = the null stream).  Calls that take a stream only enqueue work;
+ *     they return before the GPU finishes.
+ *   - Velocity grid (Sec. 4.1): n points per axis on [-L, L)^3,
+ *     v_j = (j - n/2) * 2L/n, a distribution is n^3 values in row-major
+ *     order [i1][i2][i3] (i3 fastest).  A batch is [cells][n][n][n].
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BZ_ABI_VERSION 1
+
+typedef int32_t bz_status;
+
+enum {
+  BZ_OK = 0,
+  BZ_AGAIN = 1,
+  BZ_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad enum) */
+  BZ_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
+  BZ_ERR_DEVICE = -3,      /* HIP runtime error (message in bz_last_error) */
+  BZ_ERR_NOMEM = -4,       /* caller-supplied buffer or arena too small */
+  BZ_ERR_STATE = -5,       /* call out of order (e.g. plan not bound) */
+  BZ_ERR_NUMERIC = -6      /* invalid numeric input detected */
+};
+
+/* element types of distributions and outputs */
+enum { BZ_FP64 = 0, BZ_FP32 = 1 };
+
+/* direction rules for the angular quadrature over the half sphere
+   (Sec. 4.4.1, 3D case); weights always sum to 2*pi */
+enum {
+  BZ_DIRS_EXPLICIT = 0, /* use desc.dirs / desc.weights */
+  BZ_DIRS_ICOSA6 = 1,   /* six icosahedral axes, weight pi/3 (m must be 6) */
+  BZ_DIRS_PRODUCT = 2,  /* theta_p=(p+1/2)pi/a1, phi_q=q pi/a2, weights ~ sin(theta) */
+  BZ_DIRS_SPIRAL = 3    /* equal-weight golden spiral, z_p=(p+1/2)/m */
+};
+
+/* evaluation strategy */
+enum {
+  BZ_XF_AUTO = 0,  /* fused kernel where one exists for (n, precision), else plain */
+  BZ_XF_FUSED = 1, /* fused per-direction kernel (FP32, n in {16, 32}) */
+  BZ_XF_PLAIN = 2  /* unfused pencil kernels through HBM (any precision, any n) */
+};
+
+/* bz_collide_batch flags */
+enum {
+  BZ_SCATTER = 1 /* write cell c of the output at row idx[c] instead of row c */
+};
+
+/*
+ * Plan descriptor.  Defines the discrete operator: velocity grid (n, L),
+ * truncation radius R of Q^R, decoupled kernel Btilde(x,y) = kernel_c *
+ * |x|^(gamma-1) (gamma = 1, kernel_c = 4 is the hard-sphere kernel
+ * B = |v - v*| of Sec. 2.1), and the direction rule.
+ */
+typedef struct {
+  int32_t n;             /* points per velocity axis: 16, 24, 32 or 48 */
+  double L;              /* half width of the velocity box */
+  double R;              /* truncation radius; <= 0 selects (sqrt(2)-1) L; must be
+                            <= 4L/(3+sqrt 2), the period-overlap bound of Sec. 4.4.1 */
+  double gamma;          /* kernel exponent in [0, 1] */
+  double kernel_c;       /* kernel constant; 4.0 gives B = |v - v*| at gamma = 1 */
+  int32_t m;             /* number of half-sphere directions, 1..512 */
+  int32_t dir_kind;      /* BZ_DIRS_* */
+  const double* dirs;    /* host [m][3] unit vectors (BZ_DIRS_EXPLICIT), else ignored */
+  const double* weights; /* host [m], sum 2*pi (BZ_DIRS_EXPLICIT), else ignored */
+  int32_t a1, a2;        /* BZ_DIRS_PRODUCT grid sizes, a1*a2 == m */
+  int32_t precision;     /* BZ_FP32: FP32 transforms, multipliers and products,
+                            FP32 accumulation; BZ_FP64: everything in FP64 */
+  int32_t transform;     /* BZ_XF_* */
+  int32_t project;       /* 1: FP64 conservative projection, FP64 output;
+                            0: raw Q in the plan precision */
+  int32_t max_cells;     /* largest batch the bound workspace must hold */
+  int32_t chunks;        /* fused path: direction chunks per cell (0 = auto) */
+} bz_plan_desc;
+
+typedef struct bz_plan bz_plan;
+
+/* ABI version the library was built with (BZ_ABI_VERSION). */
+int32_t bz_abi_version(void);
+
+/* Text of the calling thread's last error ("" if none).  Valid until the
+   thread's next failing call. */
+const char* bz_last_error(void);
+
+/*
+ * Build a plan on the host: validates the descriptor (BZ_ERR_ARG on
+ * unsupported n, R beyond the non-overlap bound, |sum w - 2 pi| > 1e-12,
+ * non-unit directions), generates the direction rule and evaluates in FP64
+ * the Fourier multipliers of the fast method for every direction p and wave
+ * vector kappa_k (Sec. 4.4.1, 3D case, read as):
+ *   alpha_p(k)  = phi_R(kappa_k . e_p),  phi_R(s) = 2 int_0^R r^gamma cos(r s) dr,
+ *   alpha'_p(k) = psi_R(|kappa_k - (kappa_k . e_p) e_p|), psi_R(r) = 2 pi R J1(R r)/r,
+ * the loss multiplier Bhat_M(k) = sum_p w_p alpha_p(k) alpha'_p(k), and the
+ * inverse Gram matrix of the five collision invariants (hypothesis (H1)).
+ * *out receives a heap object owned by the caller (bz_plan_destroy).
+ */
+bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out);
+
+/* Device bytes the plan needs: multiplier tables (read-only, shared by all
+   calls), and a workspace of ws_fixed + ws_per_cell * cells. */
+bz_status bz_plan_device_bytes(const bz_plan* plan, size_t* tables, size_t* ws_fixed,
+                               size_t* ws_per_cell);
+
+/* Attach caller device memory and upload the tables (asynchronous copy on
+   `stream`; the host tables stay alive inside the plan).  tables_dev must
+   hold the `tables` bytes, ws_dev ws_bytes >= ws_fixed + ws_per_cell.  Both
+   must be 256-byte aligned.  Calls that share a plan share its workspace:
+   they must be ordered on one stream. */
+bz_status bz_plan_bind(bz_plan* plan, void* tables_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream);
+
+/* Free the host plan (device buffers stay with the caller). */
+bz_status bz_plan_destroy(bz_plan* plan);
+
+/* Cells a bound plan can process per bz_collide_batch call. */
+bz_status bz_plan_capacity(const bz_plan* plan, int32_t* cells);
+
+/* Evaluation strategy the plan resolved to (BZ_XF_FUSED or BZ_XF_PLAIN). */
+bz_status bz_plan_transform(const bz_plan* plan, int32_t* transform);
+
+/* Host copies of the plan's direction rule: dirs [m][3], weights [m]. */
+bz_status bz_plan_get_rule(const bz_plan* plan, double* dirs, double* weights);
+
+/* Host copy of the FP64 multipliers of pass p (0 <= p <= m; pass m is the
+   loss pass (Bhat_M, 1)) as [k2][k3][k1][2] = (alpha_p, alpha'_p). */
+bz_status bz_plan_get_multipliers(const bz_plan* plan, int32_t p, double* out);
+
+/*
+ * Evaluate Q(f,f) for a batch of cells (Sec. 4.4.1):
+ *   fhat = DFT(f)/n^3 with Nyquist modes zeroed;
+ *   Q+   = sum_p w_p IDFT(alpha_p fhat) * IDFT(alpha'_p fhat);
+ *   Q    = kernel_c * (Q+ - IDFT(fhat) * IDFT(Bhat_M fhat));
+ *   if project: Q <- Q - C^T (C C^T)^-1 C Q (FP64; C = [1, v1, v2, v3, |v|^2]),
+ *   which restores the invariants of (H1) that periodisation loses.
+ * f:       device [*][n][n][n] of f_dtype (BZ_FP64 or BZ_FP32); cell c is row
+ *          idx[c] (idx NULL: row c).
+ * idx:     device int32 [ncells] or NULL.
+ * ncells:  cells to process, <= capacity; with ncells_dev it is the upper bound.
+ * ncells_dev: device int32 or NULL; when given, the number of cells processed
+ *          is min(*ncells_dev, ncells), read on the GPU (no host sync; for
+ *          graph capture and masks that choose the cells on the GPU).
+ * q:       device output, FP64 if the plan projects, else the plan precision;
+ *          row c (compact) or row idx[c] (flags & BZ_SCATTER).
+ * stream:  hipStream_t.  Asynchronous.  The arithmetic of a cell does not
+ *          depend on the other cells of the batch, so results are bitwise
+ *          identical for any batch composition.
+ */
+bz_status bz_collide_batch(const bz_plan* plan, const void* f, int32_t f_dtype,
+                           const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                           void* q, int32_t flags, void* stream);
+
+/* Per-stage GPU timing of bz_collide_batch, for measurement.  When enabled,
+   each call records HIP events on its stream around the forward transform,
+   the direction/loss kernel(s) and the projection (up to 512 calls are
+   kept).  bz_plan_last_times waits for the recorded calls and returns the
+   average milliseconds per call in ms[0..3] = {forward, directions,
+   projection, total} (and, if n > 4, the number of calls in ms[4]); it then
+   starts a new averaging window. */
+bz_status bz_plan_set_timing(bz_plan* plan, int32_t enable);
+bz_status bz_plan_last_times(bz_plan* plan, float* ms, int32_t n);
+
+/* Mask descriptor (Sec. 3.3, 4.5, Algorithm 1). */
+typedef struct {
+  int32_t nx, ny;           /* spatial grid, arrays are row-major [iy][ix] */
+  double dx, dy;            /* spacings */
+  double mu0, kappa0;       /* mu = mu0 sqrt(T), kappa = kappa0 sqrt(T) (hard spheres) */
+  double eta0, eta1, delta0; /* Euler<->kinetic, ES-BGK<->Boltzmann, L1 thresholds */
+  int32_t laplacian_u_mode; /* 0: Lap u = Lap ux + Lap uy (as printed); 1: vector norm */
+} bz_mask_desc;
+
+enum { BZ_CELL_SOLID = 1, BZ_CELL_FORCE_BOLTZMANN = 2 };
+#define BZ_REGIME_SOLID 255
+
+/*
+ * Regime update of Algorithm 1 for every cell, in FP64 with a fixed operation
+ * order (no contraction):
+ *   one-cell stencil clamped at the border (ghost cells copy the nearest
+ *   cell), central first differences over 2 dx / 2 dy, 5-point Laplacians
+ *   over dx*dy (Sec. 4.5);
+ *   xi1 = eps mu/(rho T), xi2 = eps^2 2 kappa^2/(3 rho^2 T^3);
+ *   eigenvalues lambda_a, lambda_b, lambda_c of V_eps1 (closed form, Sec. 4.5);
+ *   lambda_B = eps^2 (|grad T|^2/T + |grad u|^2 + sqrt((|Lap u|^2 +
+ *   |Lap rho/rho|^2)(1+T^2))) (Sec. 3.3);
+ *   2 -> 2 iff |lambda_B| > eta1, else 1; 1 -> 2 iff |lambda_B| > eta1, else
+ *   1 -> 0 iff all |lambda - 1| <= eta0 and l1dist <= delta0; 0 -> 1 iff some
+ *   |lambda - 1| > eta0.  Cells flagged SOLID get 255 and regime_in 255 stays;
+ *   FORCE_BOLTZMANN gets 2.
+ * Inputs (device, [ny][nx]): rho, ux, uy, T, eps (FP64), regime_in (u8),
+ *   l1dist (FP64, NULL: the 1 -> 0 switch never fires), cell_flags (u8, NULL
+ *   allowed).
+ * Outputs (device): regime_out [ny][nx] u8; boltz_idx int32 [nx*ny]: the
+ *   regime-2 cells as ascending linear indices iy*nx+ix; counts int32[2]:
+ *   counts[0] = number of regime-2 cells, counts[1] = number of cells whose
+ *   inputs are invalid (rho <= 0, T <= 0, eps < 0 or non-finite: those cells
+ *   keep regime_in); diag (NULL allowed) FP64 [nx*ny][4] = lambda_a,
+ *   lambda_b, lambda_c, lambda_B.  Asynchronous on `stream`.
+ */
+bz_status bz_realizability_mask(const bz_mask_desc* desc, const double* rho, const double* ux,
+                                const double* uy, const double* T, const double* eps,
+                                const uint8_t* regime_in, const double* l1dist,
+                                const uint8_t* cell_flags, uint8_t* regime_out,
+                                int32_t* boltz_idx, int32_t* counts, double* diag, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BZ_H */

@@ -117,8 +117,10 @@ def indicators(d: MaskDesc, rho, ux, uy, T, eps):
     return lam_a, lam_b, lam_c, lam_B
 
 
-def regime_update(d: MaskDesc, lam, regime_in, l1dist=None, flags=None):
-    """Algorithm 1 applied cell by cell (vectorised)."""
+def regime_update(d: MaskDesc, lam, regime_in, l1dist=None, flags=None, valid=None):
+    """Algorithm 1 applied cell by cell (vectorised).  Cells marked invalid
+    (non-positive density or temperature, negative eps, non-finite values)
+    keep their regime; regime codes other than 0, 1, 2 and 255 are kept too."""
     lam_a, lam_b, lam_c, lam_B = lam
     r = np.asarray(regime_in)
     big_B = np.abs(lam_B) > d.eta1
@@ -128,7 +130,7 @@ def regime_update(d: MaskDesc, lam, regime_in, l1dist=None, flags=None):
         close = np.zeros(r.shape, dtype=bool)
     else:
         close = np.asarray(l1dist) <= d.delta0
-    out = np.empty(r.shape, dtype=np.uint8)
+    out = r.astype(np.uint8).copy()
     # regime 2: stay iff lambda_B > eta1, else fall back to ES-BGK
     out[r == 2] = np.where(big_B, 2, 1)[r == 2]
     # regime 1: up to 2 on lambda_B; down to 0 only if V_eps1 ~ I and f ~ M
@@ -137,6 +139,8 @@ def regime_update(d: MaskDesc, lam, regime_in, l1dist=None, flags=None):
     # regime 0: up to 1 when V_eps1 leaves the identity; never to 2 directly
     out[r == 0] = np.where(near_one, 0, 1)[r == 0]
     out[r == REGIME_SOLID] = REGIME_SOLID
+    if valid is not None:
+        out[~valid] = r[~valid]
     if flags is not None:
         fl = np.asarray(flags)
         out[(fl & FORCE_BOLTZMANN) != 0] = 2
@@ -144,14 +148,24 @@ def regime_update(d: MaskDesc, lam, regime_in, l1dist=None, flags=None):
     return out
 
 
+def input_valid(rho, ux, uy, T, eps, lam):
+    """rho > 0, T > 0, eps >= 0 and every input and indicator finite."""
+    with np.errstate(invalid="ignore"):
+        ok = (rho > 0) & (T > 0) & (eps >= 0)
+    for x in (rho, ux, uy, T, eps) + tuple(lam):
+        ok &= np.isfinite(x)
+    return ok
+
+
 def realizability_mask(d: MaskDesc, rho, ux, uy, T, eps, regime_in, l1dist=None, flags=None):
     """Return (regime_out [ny][nx] uint8, ascending int32 list of regime-2
     linear indices iy*nx + ix, diag [ny*nx][4] = (lam_a, lam_b, lam_c, lam_B))."""
     lam = indicators(d, rho, ux, uy, T, eps)
-    out = regime_update(d, lam, regime_in, l1dist, flags)
+    valid = input_valid(rho, ux, uy, T, eps, lam)
+    out = regime_update(d, lam, regime_in, l1dist, flags, valid)
     idx = np.flatnonzero(out.ravel() == 2).astype(np.int32)
     diag = np.stack([x.ravel() for x in lam], axis=1)
-    return out, idx, diag
+    return out, idx, diag, int((~valid).sum())
 
 
 def margin_cells(d: MaskDesc, lam, rel: float = 1e-12) -> int:

@@ -1,0 +1,303 @@
+"""Python binding of the bz C ABI (include/bz.h).
+
+Argument marshalling only: every step of the collision operator and of the
+regime mask runs in the HIP library ``libbz.so``; torch tensors only provide
+device memory and streams.  Importing works without a GPU (the host-only
+entry points, e.g. plan construction, can be called); every call that
+launches GPU work needs the library built for gfx950 and a visible GPU.
+There is no CPU fallback: if libbz.so is missing, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbz.so")
+
+BZ_OK, BZ_AGAIN = 0, 1
+BZ_ERR_ARG, BZ_ERR_UNSUPPORTED, BZ_ERR_DEVICE, BZ_ERR_NOMEM, BZ_ERR_STATE, BZ_ERR_NUMERIC = -1, -2, -3, -4, -5, -6
+BZ_FP64, BZ_FP32 = 0, 1
+BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL = 0, 1, 2, 3
+BZ_XF_AUTO, BZ_XF_FUSED, BZ_XF_PLAIN = 0, 1, 2
+BZ_SCATTER = 1
+BZ_CELL_SOLID, BZ_CELL_FORCE_BOLTZMANN = 1, 2
+BZ_REGIME_SOLID = 255
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class BzPlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("L", ctypes.c_double),
+        ("R", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("kernel_c", ctypes.c_double),
+        ("m", ctypes.c_int32),
+        ("dir_kind", ctypes.c_int32),
+        ("dirs", _c_double_p),
+        ("weights", _c_double_p),
+        ("a1", ctypes.c_int32),
+        ("a2", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("transform", ctypes.c_int32),
+        ("project", ctypes.c_int32),
+        ("max_cells", ctypes.c_int32),
+        ("chunks", ctypes.c_int32),
+    ]
+
+
+class BzMaskDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("mu0", ctypes.c_double), ("kappa0", ctypes.c_double),
+        ("eta0", ctypes.c_double), ("eta1", ctypes.c_double), ("delta0", ctypes.c_double),
+        ("laplacian_u_mode", ctypes.c_int32),
+    ]
+
+
+class BzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bz error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+# (name, restype, argtypes) for every symbol declared in include/bz.h
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+SIGNATURES = [
+    ("bz_abi_version", _I32, []),
+    ("bz_last_error", ctypes.c_char_p, []),
+    ("bz_plan_create", _I32, [ctypes.POINTER(BzPlanDesc), ctypes.POINTER(_VP)]),
+    ("bz_plan_device_bytes", _I32, [_VP, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)]),
+    ("bz_plan_bind", _I32, [_VP, _VP, _VP, _SZ, _VP]),
+    ("bz_plan_destroy", _I32, [_VP]),
+    ("bz_plan_capacity", _I32, [_VP, ctypes.POINTER(_I32)]),
+    ("bz_plan_transform", _I32, [_VP, ctypes.POINTER(_I32)]),
+    ("bz_plan_get_rule", _I32, [_VP, _c_double_p, _c_double_p]),
+    ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
+    ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_plan_set_timing", _I32, [_VP, _I32]),
+    ("bz_plan_last_times", _I32, [_VP, ctypes.POINTER(ctypes.c_float), _I32]),
+    ("bz_realizability_mask", _I32, [ctypes.POINTER(BzMaskDesc), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                     _VP, _VP, _VP, _VP, _VP, _VP]),
+]
+
+
+def lib():
+    """Load libbz.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise BzError(code, lib().bz_last_error().decode())
+    return code
+
+
+# ---------------------------------------------------------------- C ABI, same names
+def bz_abi_version() -> int:
+    return lib().bz_abi_version()
+
+
+def bz_last_error() -> str:
+    return lib().bz_last_error().decode()
+
+
+def make_plan_desc(n: int, L: float = 8.0, R: float = 0.0, gamma: float = 1.0, kernel_c: float = 4.0,
+                   m: int = 6, dir_kind: int = BZ_DIRS_ICOSA6, dirs=None, weights=None, a1: int = 0,
+                   a2: int = 0, precision: int = BZ_FP32, transform: int = BZ_XF_AUTO, project: int = 1,
+                   max_cells: int = 1, chunks: int = 0) -> BzPlanDesc:
+    d = BzPlanDesc()
+    d.n, d.L, d.R, d.gamma, d.kernel_c = n, L, R, gamma, kernel_c
+    d.m, d.dir_kind, d.a1, d.a2 = m, dir_kind, a1, a2
+    d.precision, d.transform, d.project, d.max_cells, d.chunks = precision, transform, project, max_cells, chunks
+    d._keep = []
+    if dirs is not None:
+        import numpy as np
+        da = np.ascontiguousarray(dirs, dtype=np.float64).ravel()
+        wa = np.ascontiguousarray(weights, dtype=np.float64).ravel()
+        d._keep = [da, wa]
+        d.dirs = da.ctypes.data_as(_c_double_p)
+        d.weights = wa.ctypes.data_as(_c_double_p)
+        d.dir_kind = BZ_DIRS_EXPLICIT
+        d.m = len(wa)
+    return d
+
+
+def bz_plan_create(desc: BzPlanDesc) -> int:
+    out = _VP()
+    _check(lib().bz_plan_create(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def bz_plan_device_bytes(plan: int):
+    t, f, c = _SZ(), _SZ(), _SZ()
+    _check(lib().bz_plan_device_bytes(plan, ctypes.byref(t), ctypes.byref(f), ctypes.byref(c)))
+    return t.value, f.value, c.value
+
+
+def bz_plan_bind(plan: int, tables_dev: int, ws_dev: int, ws_bytes: int, stream: int = 0) -> None:
+    _check(lib().bz_plan_bind(plan, tables_dev, ws_dev, ws_bytes, stream))
+
+
+def bz_plan_destroy(plan: int) -> None:
+    _check(lib().bz_plan_destroy(plan))
+
+
+def bz_plan_capacity(plan: int) -> int:
+    c = _I32()
+    _check(lib().bz_plan_capacity(plan, ctypes.byref(c)))
+    return c.value
+
+
+def bz_plan_transform(plan: int) -> int:
+    c = _I32()
+    _check(lib().bz_plan_transform(plan, ctypes.byref(c)))
+    return c.value
+
+
+def bz_plan_get_rule(plan: int, m: int):
+    import numpy as np
+    d = np.zeros((m, 3))
+    w = np.zeros(m)
+    _check(lib().bz_plan_get_rule(plan, d.ctypes.data_as(_c_double_p), w.ctypes.data_as(_c_double_p)))
+    return d, w
+
+
+def bz_plan_get_multipliers(plan: int, n: int, p: int):
+    """FP64 host multipliers of pass p as ([k1][k2][k3] alpha, alpha')."""
+    import numpy as np
+    buf = np.zeros(n ** 3 * 2)
+    _check(lib().bz_plan_get_multipliers(plan, p, buf.ctypes.data_as(_c_double_p)))
+    t = buf.reshape(n, n, n, 2)  # [k2][k3][k1]
+    return t[..., 0].transpose(2, 0, 1).copy(), t[..., 1].transpose(2, 0, 1).copy()
+
+
+def bz_collide_batch(plan: int, f: int, f_dtype: int, idx: int, ncells: int, ncells_dev: int,
+                     q: int, flags: int = 0, stream: int = 0) -> None:
+    _check(lib().bz_collide_batch(plan, f, f_dtype, idx, ncells, ncells_dev, q, flags, stream))
+
+
+def bz_plan_set_timing(plan: int, enable: bool) -> None:
+    _check(lib().bz_plan_set_timing(plan, 1 if enable else 0))
+
+
+def bz_plan_last_times(plan: int):
+    ms = (ctypes.c_float * 5)()
+    _check(lib().bz_plan_last_times(plan, ms, 5))
+    return list(ms)
+
+
+def bz_realizability_mask(desc: BzMaskDesc, rho: int, ux: int, uy: int, T: int, eps: int,
+                          regime_in: int, l1dist: int, cell_flags: int, regime_out: int,
+                          boltz_idx: int, counts: int, diag: int, stream: int = 0) -> None:
+    _check(lib().bz_realizability_mask(ctypes.byref(desc), rho, ux, uy, T, eps, regime_in, l1dist,
+                                       cell_flags, regime_out, boltz_idx, counts, diag, stream))
+
+
+# ---------------------------------------------------------------- torch-side helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Collider:
+    """A bound plan whose tables and workspace are torch tensors on the GPU."""
+
+    def __init__(self, n: int, max_cells: int, device="cuda", stream=None, **desc_kw):
+        torch = _torch()
+        self.desc = make_plan_desc(n=n, max_cells=max_cells, **desc_kw)
+        self.n = n
+        self.plan = bz_plan_create(self.desc)
+        tb, fixed, per = bz_plan_device_bytes(self.plan)
+        self.tables = torch.empty(max(tb, 256), dtype=torch.uint8, device=device)
+        self.ws_bytes = fixed + per * max_cells
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        bz_plan_bind(self.plan, _ptr(self.tables), _ptr(self.ws), self.ws_bytes, _stream(stream))
+        self.capacity = bz_plan_capacity(self.plan)
+        self.transform = bz_plan_transform(self.plan)
+        self.out_dtype = torch.float64 if self.desc.project or self.desc.precision == BZ_FP64 else torch.float32
+
+    def __call__(self, f, idx=None, ncells=None, ncells_dev=None, out=None, scatter=False, stream=None):
+        torch = _torch()
+        n3 = self.n ** 3
+        if f.dtype not in (torch.float32, torch.float64) or not f.is_contiguous() or not f.is_cuda:
+            raise ValueError("f must be a contiguous CUDA float32/float64 tensor")
+        if ncells is None:
+            ncells = idx.numel() if idx is not None else f.numel() // n3
+        if idx is not None and (idx.dtype != torch.int32 or not idx.is_cuda):
+            raise ValueError("idx must be a CUDA int32 tensor")
+        if out is None:
+            out = torch.empty((ncells, self.n, self.n, self.n), dtype=self.out_dtype, device=f.device)
+        fd = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
+        bz_collide_batch(self.plan, _ptr(f), fd, _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
+                         BZ_SCATTER if scatter else 0, _stream(stream))
+        return out
+
+    def close(self):
+        if self.plan:
+            bz_plan_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def realizability_mask(desc: BzMaskDesc, rho, ux, uy, T, eps, regime_in, l1dist=None, cell_flags=None,
+                       with_diag=False, stream=None):
+    """Run bz_realizability_mask on torch CUDA tensors; returns (regime_out,
+    boltz_idx, counts, diag)."""
+    torch = _torch()
+    dev = rho.device
+    ncell = desc.nx * desc.ny
+    rout = torch.empty_like(regime_in)
+    idx = torch.empty(ncell, dtype=torch.int32, device=dev)
+    counts = torch.empty(2, dtype=torch.int32, device=dev)
+    diag = torch.empty((ncell, 4), dtype=torch.float64, device=dev) if with_diag else None
+    bz_realizability_mask(desc, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(eps), _ptr(regime_in),
+                          _ptr(l1dist), _ptr(cell_flags), _ptr(rout), _ptr(idx), _ptr(counts),
+                          _ptr(diag), _stream(stream))
+    return rout, idx, counts, diag
+
+
+def mask_desc(nx, ny, dx, dy, mu0=1.0, kappa0=15.0 / 4.0, eta0=1e-3, eta1=1e-4, delta0=1e-4,
+              laplacian_u_mode=0) -> BzMaskDesc:
+    d = BzMaskDesc()
+    d.nx, d.ny, d.dx, d.dy = nx, ny, dx, dy
+    d.mu0, d.kappa0, d.eta0, d.eta1, d.delta0 = mu0, kappa0, eta0, eta1, delta0
+    d.laplacian_u_mode = laplacian_u_mode
+    return d
+
+
+def default_R(L: float) -> float:
+    return (math.sqrt(2.0) - 1.0) * L

@@ -1,0 +1,70 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bz.h"
+
+namespace bz {
+
+// Thread-local last-error text; every failing entry point sets it.
+bz_status fail(bz_status code, const char* fmt, ...);
+void clear_error();
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace regions of a bound plan, each [capacity][...].
+struct WsLayout {
+  size_t fh_off, y_off, acc_off;  // byte offsets into ws_dev
+  size_t fh_cell, y_cell, acc_cell;  // bytes per cell of each region
+};
+
+}  // namespace bz
+
+struct bz_plan {
+  bz_plan_desc d{};  // copy of the descriptor (dirs/weights pointers cleared)
+  int n = 0;         // points per axis
+  int m = 0;         // directions
+  int m1 = 0;        // m + 1: the loss term is evaluated as one more pass
+  double L = 0, R = 0, gamma = 1, C = 4, dv = 0;
+  int fp32 = 1;      // plan precision
+  int project = 1;
+  int transform = BZ_XF_PLAIN;  // resolved strategy
+  int chunks = 1;               // direction chunks per cell (fused path)
+  std::vector<double> dirs;     // [m][3]
+  std::vector<double> w;        // [m]
+  // FP64 host tables in device layout [p][k2][k3][k1] x (a, a'), p < m1;
+  // pass p = m carries (Bhat_M, 1) with weight -1.
+  std::vector<double> mult;
+  std::vector<double> wext;     // [m1]
+  double ginv[25] = {};         // (C C^T)^-1 of the five invariants
+  size_t table_mult_bytes = 0, table_w_off = 0, tables_bytes = 0;
+  size_t ws_fixed = 0, ws_per_cell = 0;
+  // binding
+  void* tables_dev = nullptr;
+  void* ws_dev = nullptr;
+  size_t ws_bytes = 0;
+  int capacity = 0;
+  bz::WsLayout ws{};
+  // timing: a ring of event quadruples, one per timed call
+  static constexpr int kTimingSlots = 512;
+  bool timing = false;
+  bool events_ready = false;
+  std::vector<hipEvent_t> evs;  // 4 per slot
+  int timed_calls = 0;          // calls recorded since the last summary
+  hipEvent_t* ev = nullptr;     // quadruple of the current call
+};
+
+namespace bz {
+// kernel launchers (collide.hip)
+bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int32_t* idx,
+                         int ncells, const int32_t* ncells_dev, void* q, int scatter,
+                         hipStream_t s);
+bool fused_supported(int n, int fp32);
+int fused_default_chunks(int n);
+}  // namespace bz

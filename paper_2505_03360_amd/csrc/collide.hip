@@ -1,0 +1,530 @@
+// Kernels of the fast spectral collision operator (Sec. 4.4.1) for gfx950.
+//
+// Per cell, with fhat = DFT(f)/n^3 (Nyquist zeroed) and, for every pass p of
+// the direction list extended by the loss pass:
+//   X_p = (alpha_p + i alpha'_p) * fhat         (both multipliers are real and even)
+//   Y_p = IDFT(X_p) = IDFT(alpha_p fhat) + i IDFT(alpha'_p fhat)
+//   acc += w_p * Re(Y_p) * Im(Y_p)
+// Both inverse transforms of a direction are real, so one complex transform
+// carries the pair.  The loss pass has multipliers (Bhat_M, 1) and weight -1,
+// which adds -IDFT(Bhat_M fhat) * IDFT(fhat).  The result kernel_c * acc is
+// Q(f,f); the FP64 projection kernel removes its component along the five
+// collision invariants.
+//
+// Layouts (per cell, n^3 entries): f and q [i1][i2][i3]; fhat, multipliers
+// [k2][k3][k1] (k1 fastest, so that stage-A pencils along k3 are read with
+// consecutive lanes on consecutive k1); acc [j1][j2][j3].
+//
+// Two evaluation strategies share the forward transform and the projection:
+//   plain: three pencil passes per direction through HBM, one thread per
+//          pencil (any n, FP32 or FP64);
+//   fused: one workgroup per (cell, direction chunk) runs every direction of
+//          its chunk on chip: stage-A pencils along k3 in registers, two
+//          transposes through LDS (in j3 slices), stage-C pencils along k1 in
+//          registers, and the products accumulated in registers (FP32).
+#include "bz_internal.hpp"
+#include "fft.hpp"
+
+using bzk::cx;
+
+namespace {
+
+__device__ __forceinline__ int live_count(int ncells, const int32_t* ncells_dev) {
+  int c = ncells;
+  if (ncells_dev) {
+    const int d = *ncells_dev;
+    c = d < c ? d : c;
+    if (c < 0) c = 0;
+  }
+  return c;
+}
+
+template <typename T>
+struct PlainArgs {
+  const void* f;
+  int f_fp32;
+  const int32_t* idx;
+  int ncells;
+  const int32_t* ncells_dev;
+  cx<T>* fh;  // [cell][k2][k3][k1]
+  cx<T>* y;   // [cell][...]
+  T* acc;     // [cell][chunks][j1][j2][j3]
+  size_t fh_stride, y_stride, acc_stride;  // elements per cell
+  const cx<T>* mult;  // [pass][k2][k3][k1]
+  const T* w;         // [pass]
+  int pass;
+  int first;
+};
+
+// ------------------------------------------------------------------ forward
+// pass 1: pencils along i1, thread (cell, i2, i3); f -> y[cell][k1][i2][i3]
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fwd1(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int i2 = rem / N, i3 = rem % N;
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+  const size_t base = size_t(row) * N * N * N + size_t(i2) * N + i3;
+  cx<T> x[N];
+  if (a.f_fp32) {
+    const float* f = static_cast<const float*>(a.f) + base;
+#pragma unroll
+    for (int i1 = 0; i1 < N; ++i1) x[i1] = {T(f[size_t(i1) * N * N]), T(0)};
+  } else {
+    const double* f = static_cast<const double*>(a.f) + base;
+#pragma unroll
+    for (int i1 = 0; i1 < N; ++i1) x[i1] = {T(f[size_t(i1) * N * N]), T(0)};
+  }
+  bzk::fft<N, -1>(x);
+  cx<T>* y = a.y + c * a.y_stride + size_t(i2) * N + i3;
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) y[size_t(k1) * N * N] = x[k1];
+}
+
+// pass 2: pencils along i2, thread (cell, k1, i3), in place in y
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fwd2(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int k1 = rem / N, i3 = rem % N;
+  cx<T>* y = a.y + c * a.y_stride + size_t(k1) * N * N + i3;
+  cx<T> x[N];
+#pragma unroll
+  for (int i2 = 0; i2 < N; ++i2) x[i2] = y[i2 * N];
+  bzk::fft<N, -1>(x);
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) y[k2 * N] = x[k2];
+}
+
+// pass 3: pencils along i3, thread (cell, k2, k1); scale by n^-3, zero the
+// Nyquist modes, write fhat[cell][k2][k3][k1]
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fwd3(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int k2 = rem / N, k1 = rem % N;
+  const cx<T>* y = a.y + c * a.y_stride + size_t(k1) * N * N + size_t(k2) * N;
+  cx<T> x[N];
+#pragma unroll
+  for (int i3 = 0; i3 < N; ++i3) x[i3] = y[i3];
+  bzk::fft<N, -1>(x);
+  const T scale = T(1.0 / (double(N) * N * N));
+  const bool nyq12 = (k1 == N / 2) || (k2 == N / 2);
+  cx<T>* fh = a.fh + c * a.fh_stride + size_t(k2) * N * N + k1;
+#pragma unroll
+  for (int k3 = 0; k3 < N; ++k3) {
+    const bool z = nyq12 || (k3 == N / 2);
+    fh[size_t(k3) * N] = z ? cx<T>{T(0), T(0)} : cx<T>{x[k3].x * scale, x[k3].y * scale};
+  }
+}
+
+// ------------------------------------------------------------------ plain passes
+// pass A: X = (alpha + i alpha') fhat, inverse along k3; thread (cell, k2, k1)
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_dirA(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int k2 = rem / N, k1 = rem % N;
+  const size_t off = size_t(k2) * N * N + k1;
+  const cx<T>* fh = a.fh + c * a.fh_stride + off;
+  const cx<T>* mu = a.mult + size_t(a.pass) * N * N * N + off;
+  cx<T> x[N];
+#pragma unroll
+  for (int k3 = 0; k3 < N; ++k3) {
+    const cx<T> F = fh[size_t(k3) * N];
+    const cx<T> M = mu[size_t(k3) * N];
+    x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+  }
+  bzk::fft<N, 1>(x);
+  cx<T>* y = a.y + c * a.y_stride + off;
+#pragma unroll
+  for (int j3 = 0; j3 < N; ++j3) y[size_t(j3) * N] = x[j3];
+}
+
+// pass B: inverse along k2; y[cell][k2][j3][k1] -> y[cell][j2][j3][k1]; thread (cell, j3, k1)
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_dirB(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int j3 = rem / N, k1 = rem % N;
+  cx<T>* y = a.y + c * a.y_stride + size_t(j3) * N + k1;
+  cx<T> x[N];
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) x[k2] = y[size_t(k2) * N * N];
+  bzk::fft<N, 1>(x);
+#pragma unroll
+  for (int j2 = 0; j2 < N; ++j2) y[size_t(j2) * N * N] = x[j2];
+}
+
+// pass C: inverse along k1 and accumulate w Re Im into acc[cell][j1][j2][j3];
+// thread (cell, j2, j3)
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int j2 = rem / N, j3 = rem % N;
+  const cx<T>* y = a.y + c * a.y_stride + size_t(j2) * N * N + size_t(j3) * N;
+  cx<T> x[N];
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) x[k1] = y[k1];
+  bzk::fft<N, 1>(x);
+  const T wp = a.w[a.pass];
+  T* acc = a.acc + c * a.acc_stride + size_t(j2) * N + j3;
+  if (a.first) {
+#pragma unroll
+    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] = wp * x[j1].x * x[j1].y;
+  } else {
+#pragma unroll
+    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] += wp * x[j1].x * x[j1].y;
+  }
+}
+
+// ------------------------------------------------------------------ fused FP32
+struct FusedArgs {
+  int ncells;
+  const int32_t* ncells_dev;
+  const cx<float>* fh;
+  size_t fh_stride;
+  float* acc;
+  size_t acc_stride;  // per cell (all chunks)
+  const cx<float>* mult;
+  const float* w;
+  int m1, chunks;
+};
+
+// N^2/S threads; S j3-slices of width W = N/S.
+//   stage A: thread t owns pencils P = a*T + t (a < S) along k3 at
+//            (k1, k2) = (P % N, P / N);
+//   stage B: thread t owns, in every slice, the pencil along k2 at
+//            (k1, j3) = (t / W, s*W + t % W);
+//   stage C: thread t owns, in every slice, the pencil along k1 at
+//            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
+// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
+// lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
+template <int N, int S>
+__global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
+  constexpr int T = N * N / S;
+  constexpr int W = N / S;
+  constexpr int AB = W + 1;
+  __shared__ cx<float> lds[N * N * AB];
+  const int cell = blockIdx.x / a.chunks;
+  const int chunk = blockIdx.x % a.chunks;
+  if (cell >= live_count(a.ncells, a.ncells_dev)) return;
+  const int p0 = int((long(chunk) * a.m1) / a.chunks);
+  const int p1 = int((long(chunk + 1) * a.m1) / a.chunks);
+  const int t = threadIdx.x;
+  const int tb_k1 = t / W, tl = t % W;  // stage B: k1, j3 % W; stage C: j2, j3 % W
+  const cx<float>* fhc = a.fh + cell * a.fh_stride;
+  float acc[S][N];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[s][j] = 0.0f;
+
+  for (int p = p0; p < p1; ++p) {
+    const cx<float>* mp = a.mult + size_t(p) * N * N * N;
+    const float wp = a.w[p];
+    cx<float> ra[S][N];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int P = q * T + t;
+      const int k1 = P % N, k2 = P / N;
+      const size_t off = size_t(k2) * N * N + k1;
+#pragma unroll
+      for (int k3 = 0; k3 < N; ++k3) {
+        const cx<float> F = fhc[off + size_t(k3) * N];
+        const cx<float> M = mp[off + size_t(k3) * N];
+        ra[q][k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+      }
+      bzk::fft<N, 1>(ra[q]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const int P = q * T + t;
+        const int k1 = P % N, k2 = P / N;
+#pragma unroll
+        for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = ra[q][s * W + j];
+      }
+      __syncthreads();
+      cx<float> rb[N];
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
+      bzk::fft<N, 1>(rb);
+      __syncthreads();
+#pragma unroll
+      for (int j2 = 0; j2 < N; ++j2) lds[(j2 * N + tb_k1) * W + tl] = rb[j2];
+      __syncthreads();
+      cx<float> rc[N];
+#pragma unroll
+      for (int k1 = 0; k1 < N; ++k1) rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
+      bzk::fft<N, 1>(rc);
+#pragma unroll
+      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += wp * rc[j1].x * rc[j1].y;
+    }
+  }
+  float* out = a.acc + cell * a.acc_stride + size_t(chunk) * N * N * N;
+  const int j2 = tb_k1;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j1 = 0; j1 < N; ++j1) out[size_t(j1) * N * N + size_t(j2) * N + s * W + tl] = acc[s][j1];
+}
+
+// ------------------------------------------------------------------ projection
+struct ProjArgs {
+  int n;
+  int ncells;
+  const int32_t* ncells_dev;
+  const int32_t* idx;
+  int scatter;
+  const void* acc;  // [cell][chunks][n^3] of float or double
+  int acc_fp32;
+  size_t acc_stride;  // elements per cell
+  int chunks;
+  double C, dv;
+  double ginv[25];
+  int project;  // 1: FP64 projection, FP64 output
+  void* q;
+  int q_fp32;   // output type when project == 0
+};
+
+__device__ __forceinline__ double load_acc(const ProjArgs& a, size_t i) {
+  return a.acc_fp32 ? double(static_cast<const float*>(a.acc)[i]) : static_cast<const double*>(a.acc)[i];
+}
+
+// One workgroup per cell.  qr_j = C * sum_chunks acc; moments m = C qr
+// (1, v1, v2, v3, |v|^2) reduced in a fixed order; lambda = G^-1 m;
+// q_j = qr_j - (l0 + l1 v1 + l2 v2 + l3 v3 + l4 |v|^2).
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+  const int c = blockIdx.x;
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int n = a.n;
+  const size_t n3 = size_t(n) * n * n;
+  const size_t base = size_t(c) * a.acc_stride;
+  const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
+  const int t = threadIdx.x;
+  auto qraw = [&](size_t j) {
+    double s = 0.0;
+    for (int ch = 0; ch < a.chunks; ++ch) s += load_acc(a, base + size_t(ch) * n3 + j);
+    return a.C * s;
+  };
+  if (!a.project) {
+    for (size_t j = t; j < n3; j += blockDim.x) {
+      const double v = qraw(j);
+      if (a.q_fp32) static_cast<float*>(a.q)[row * n3 + j] = float(v);
+      else static_cast<double*>(a.q)[row * n3 + j] = v;
+    }
+    return;
+  }
+  double m[5] = {0, 0, 0, 0, 0};
+  for (size_t j = t; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
+    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
+    const double qv = qraw(j);
+    m[0] += qv;
+    m[1] += v1 * qv;
+    m[2] += v2 * qv;
+    m[3] += v3 * qv;
+    m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
+  }
+  __shared__ double red[5][256];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) red[k][t] = m[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + h];
+    __syncthreads();
+  }
+  double lam[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s += a.ginv[5 * i + k] * red[k][0];
+    lam[i] = s;
+  }
+  double* q = static_cast<double*>(a.q) + row * n3;
+  for (size_t j = t; j < n3; j += blockDim.x) {
+    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
+    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
+    const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
+    q[j] = qraw(j) - corr;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int N>
+void launch_plain_forward(const PlainArgs<T>& a, int ncells, hipStream_t s) {
+  const long threads = long(ncells) * N * N;
+  const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+  hipLaunchKernelGGL((k_fwd1<T, N>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((k_fwd2<T, N>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((k_fwd3<T, N>), grid, block, 0, s, a);
+}
+
+template <typename T, int N>
+void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
+  const long threads = long(ncells) * N * N;
+  const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+  for (int p = 0; p < m1; ++p) {
+    a.pass = p;
+    a.first = p == 0;
+    hipLaunchKernelGGL((k_dirA<T, N>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_dirB<T, N>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_dirC<T, N>), grid, block, 0, s, a);
+  }
+}
+
+template <typename T>
+bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStream_t s, bool fwd_only) {
+  switch (p->n) {
+    case 16:
+      launch_plain_forward<T, 16>(a, ncells, s);
+      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (!fwd_only) launch_plain_dirs<T, 16>(a, ncells, p->m1, s);
+      break;
+    case 24:
+      launch_plain_forward<T, 24>(a, ncells, s);
+      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (!fwd_only) launch_plain_dirs<T, 24>(a, ncells, p->m1, s);
+      break;
+    case 32:
+      launch_plain_forward<T, 32>(a, ncells, s);
+      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (!fwd_only) launch_plain_dirs<T, 32>(a, ncells, p->m1, s);
+      break;
+    case 48:
+      launch_plain_forward<T, 48>(a, ncells, s);
+      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (!fwd_only) launch_plain_dirs<T, 48>(a, ncells, p->m1, s);
+      break;
+    default:
+      return bz::fail(BZ_ERR_UNSUPPORTED, "plain path: n=%d", p->n);
+  }
+  return BZ_OK;
+}
+
+template <int N, int S>
+void launch_fused(const FusedArgs& a, int ncells, hipStream_t s) {
+  const dim3 grid(unsigned(ncells * a.chunks)), block(N * N / S);
+  hipLaunchKernelGGL((k_collide_fused<N, S>), grid, block, 0, s, a);
+}
+
+}  // namespace
+
+namespace bz {
+
+bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
+
+int fused_default_chunks(int n) { return 1; }
+
+bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int32_t* idx,
+                         int ncells, const int32_t* ncells_dev, void* q, int scatter,
+                         hipStream_t s) {
+  bz_plan* pm = const_cast<bz_plan*>(p);
+  char* ws = static_cast<char*>(p->ws_dev);
+  const size_t n3 = size_t(p->n) * p->n * p->n;
+  if (p->timing) {
+    pm->ev = &pm->evs[4 * (pm->timed_calls % bz_plan::kTimingSlots)];
+    (void)hipEventRecord(pm->ev[0], s);
+  }
+  ProjArgs pa{};
+  pa.n = p->n;
+  pa.ncells = ncells;
+  pa.ncells_dev = ncells_dev;
+  pa.idx = idx;
+  pa.scatter = scatter;
+  pa.acc = ws + p->ws.acc_off;
+  pa.acc_fp32 = p->fp32;
+  pa.chunks = p->transform == BZ_XF_FUSED ? p->chunks : 1;
+  pa.acc_stride = p->ws.acc_cell / (p->fp32 ? 4 : 8);
+  pa.C = p->C;
+  pa.dv = p->dv;
+  for (int i = 0; i < 25; ++i) pa.ginv[i] = p->ginv[i];
+  pa.project = p->project;
+  pa.q = q;
+  pa.q_fp32 = p->fp32;
+  bz_status st = BZ_OK;
+  if (p->fp32) {
+    PlainArgs<float> a{};
+    a.f = f;
+    a.f_fp32 = f_fp32;
+    a.idx = idx;
+    a.ncells = ncells;
+    a.ncells_dev = ncells_dev;
+    a.fh = reinterpret_cast<cx<float>*>(ws + p->ws.fh_off);
+    a.y = reinterpret_cast<cx<float>*>(ws + p->ws.y_off);
+    a.acc = reinterpret_cast<float*>(ws + p->ws.acc_off);
+    a.fh_stride = p->ws.fh_cell / sizeof(cx<float>);
+    a.y_stride = p->ws.y_cell / sizeof(cx<float>);
+    a.acc_stride = p->ws.acc_cell / sizeof(float);
+    a.mult = static_cast<const cx<float>*>(p->tables_dev);
+    a.w = reinterpret_cast<const float*>(static_cast<const char*>(p->tables_dev) + p->table_w_off);
+    if (p->transform == BZ_XF_FUSED) {
+      st = run_plain<float>(p, a, ncells, s, true);
+      if (st != BZ_OK) return st;
+      FusedArgs fa{};
+      fa.ncells = ncells;
+      fa.ncells_dev = ncells_dev;
+      fa.fh = a.fh;
+      fa.fh_stride = a.fh_stride;
+      fa.acc = a.acc;
+      fa.acc_stride = a.acc_stride;
+      fa.mult = a.mult;
+      fa.w = a.w;
+      fa.m1 = p->m1;
+      fa.chunks = p->chunks;
+      if (p->n == 32) launch_fused<32, 2>(fa, ncells, s);
+      else if (p->n == 16) launch_fused<16, 1>(fa, ncells, s);
+      else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
+    } else {
+      st = run_plain<float>(p, a, ncells, s, false);
+    }
+  } else {
+    PlainArgs<double> a{};
+    a.f = f;
+    a.f_fp32 = f_fp32;
+    a.idx = idx;
+    a.ncells = ncells;
+    a.ncells_dev = ncells_dev;
+    a.fh = reinterpret_cast<cx<double>*>(ws + p->ws.fh_off);
+    a.y = reinterpret_cast<cx<double>*>(ws + p->ws.y_off);
+    a.acc = reinterpret_cast<double*>(ws + p->ws.acc_off);
+    a.fh_stride = p->ws.fh_cell / sizeof(cx<double>);
+    a.y_stride = p->ws.y_cell / sizeof(cx<double>);
+    a.acc_stride = p->ws.acc_cell / sizeof(double);
+    a.mult = static_cast<const cx<double>*>(p->tables_dev);
+    a.w = reinterpret_cast<const double*>(static_cast<const char*>(p->tables_dev) + p->table_w_off);
+    st = run_plain<double>(p, a, ncells, s, false);
+  }
+  if (st != BZ_OK) return st;
+  if (p->timing) (void)hipEventRecord(pm->ev[2], s);
+  hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  if (p->timing) {
+    (void)hipEventRecord(pm->ev[3], s);
+    pm->timed_calls += 1;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(BZ_ERR_DEVICE, "bz_collide_batch: launch failed: %s", hipGetErrorString(e));
+  (void)n3;
+  return BZ_OK;
+}
+
+}  // namespace bz

@@ -1,0 +1,474 @@
+// Host side of the collision library: descriptor validation, direction rules,
+// FP64 multiplier tables of the fast spectral method (Sec. 4.4.1), the
+// inverse Gram matrix of the collision invariants, device binding and the
+// C-ABI entry points of the plan.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+#include "bz_internal.hpp"
+
+namespace bz {
+
+static thread_local std::string g_err;
+
+bz_status fail(bz_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------------------------------------------------------- direction rules
+// All rules cover the half sphere; the angular integrand of the fast method
+// is even in e, and the weights sum to the half-sphere area 2 pi.
+void rule_icosa6(std::vector<double>& d, std::vector<double>& w) {
+  const double g = (1.0 + std::sqrt(5.0)) / 2.0;
+  const double raw[6][3] = {{0, 1, g}, {0, -1, g}, {1, g, 0}, {-1, g, 0}, {g, 0, 1}, {-g, 0, 1}};
+  const double s = 1.0 / std::sqrt(1.0 + g * g);
+  d.assign(18, 0.0);
+  w.assign(6, kPi / 3.0);
+  for (int i = 0; i < 6; ++i)
+    for (int c = 0; c < 3; ++c) d[3 * i + c] = raw[i][c] * s;
+}
+
+void rule_product(int a1, int a2, std::vector<double>& d, std::vector<double>& w) {
+  d.clear();
+  w.clear();
+  double sum = 0.0;
+  for (int p = 0; p < a1; ++p) {
+    const double th = (p + 0.5) * kPi / a1;
+    for (int q = 0; q < a2; ++q) {
+      const double ph = q * kPi / a2;
+      d.push_back(std::sin(th) * std::cos(ph));
+      d.push_back(std::sin(th) * std::sin(ph));
+      d.push_back(std::cos(th));
+      w.push_back(std::sin(th));
+      sum += std::sin(th);
+    }
+  }
+  for (double& x : w) x *= 2.0 * kPi / sum;
+}
+
+void rule_spiral(int m, std::vector<double>& d, std::vector<double>& w) {
+  const double g = (1.0 + std::sqrt(5.0)) / 2.0;
+  d.resize(3 * m);
+  w.assign(m, 2.0 * kPi / m);
+  for (int p = 0; p < m; ++p) {
+    const double z = (p + 0.5) / m;
+    const double az = 2.0 * kPi * p / g;
+    const double s = std::sqrt(1.0 - z * z);
+    d[3 * p] = s * std::cos(az);
+    d[3 * p + 1] = s * std::sin(az);
+    d[3 * p + 2] = z;
+  }
+}
+
+// ---------------------------------------------------------------- special functions
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
+// three-term recurrence of P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+struct PhiEval {
+  double R, gamma;
+  std::vector<double> t2, wt;  // quadrature in t (rho = R t^2) for gamma not in {0,1}
+  explicit PhiEval(double R_, double g_) : R(R_), gamma(g_) {
+    if (gamma != 0.0 && gamma != 1.0) {
+      std::vector<double> x, w;
+      gauss_legendre(256, x, w);
+      t2.resize(x.size());
+      wt.resize(x.size());
+      for (size_t i = 0; i < x.size(); ++i) {
+        const double t = 0.5 * (x[i] + 1.0);
+        t2[i] = t * t;
+        wt[i] = 0.5 * w[i] * std::pow(t, 2.0 * gamma + 1.0);
+      }
+    }
+  }
+  static double sinc(double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; }
+  // phi_R(s) = 2 int_0^R r^gamma cos(r s) dr
+  double operator()(double s) const {
+    if (gamma == 1.0) {
+      const double a = sinc(R * s), b = sinc(0.5 * R * s);
+      return R * R * (2.0 * a - b * b);
+    }
+    if (gamma == 0.0) return 2.0 * R * sinc(R * s);
+    double acc = 0.0;
+    for (size_t i = 0; i < t2.size(); ++i) acc += wt[i] * std::cos(R * s * t2[i]);
+    return 4.0 * std::pow(R, gamma + 1.0) * acc;
+  }
+};
+
+// psi_R(r) = 2 pi R J1(R r) / r, pi R^2 at r = 0 (integral over the disc of
+// radius R in the plane normal to the direction).
+double psi_R(double r, double R) {
+  if (r == 0.0) return kPi * R * R;
+  return 2.0 * kPi * R * ::j1(R * r) / r;
+}
+
+// 5x5 symmetric positive definite inverse by Cholesky.
+bool spd_inverse5(const double G[25], double out[25]) {
+  double Lc[25] = {};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = G[5 * i + j];
+      for (int k = 0; k < j; ++k) s -= Lc[5 * i + k] * Lc[5 * j + k];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        Lc[5 * i + i] = std::sqrt(s);
+      } else {
+        Lc[5 * i + j] = s / Lc[5 * j + j];
+      }
+    }
+  // columns of the inverse: solve L L^T x = e_c
+  for (int c = 0; c < 5; ++c) {
+    double y[5], x[5];
+    for (int i = 0; i < 5; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= Lc[5 * i + k] * y[k];
+      y[i] = s / Lc[5 * i + i];
+    }
+    for (int i = 4; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < 5; ++k) s -= Lc[5 * k + i] * x[k];
+      x[i] = s / Lc[5 * i + i];
+    }
+    for (int i = 0; i < 5; ++i) out[5 * i + c] = x[i];
+  }
+  return true;
+}
+
+void build_tables(bz_plan* p) {
+  const int n = p->n, n3 = n * n * n;
+  std::vector<double> kap(n);
+  for (int k = 0; k < n; ++k) kap[k] = (kPi / p->L) * double(k < n / 2 ? k : k - n);
+  p->mult.assign(size_t(p->m1) * n3 * 2, 0.0);
+  PhiEval phi(p->R, p->gamma);
+  auto work = [&](int p0, int p1) {
+    for (int dir = p0; dir < p1; ++dir) {
+      const double e0 = p->dirs[3 * dir], e1 = p->dirs[3 * dir + 1], e2 = p->dirs[3 * dir + 2];
+      double* out = &p->mult[size_t(dir) * n3 * 2];
+      for (int k2 = 0; k2 < n; ++k2)
+        for (int k3 = 0; k3 < n; ++k3)
+          for (int k1 = 0; k1 < n; ++k1) {
+            const double q1 = kap[k1], q2 = kap[k2], q3 = kap[k3];
+            const double s = q1 * e0 + q2 * e1 + q3 * e2;
+            const double r1 = q1 - s * e0, r2 = q2 - s * e1, r3 = q3 - s * e2;
+            const double r = std::sqrt(r1 * r1 + r2 * r2 + r3 * r3);
+            const size_t o = 2 * ((size_t(k2) * n + k3) * n + k1);
+            out[o] = phi(s);
+            out[o + 1] = psi_R(r, p->R);
+          }
+    }
+  };
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = int(std::max(1u, std::min(hw, 16u)));
+  nt = std::min(nt, p->m);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back(work, p->m * t / nt, p->m * (t + 1) / nt);
+  for (auto& x : th) x.join();
+  // loss pass: (Bhat_M, 1), Bhat_M(k) = sum_p w_p alpha_p(k) alpha'_p(k)
+  double* loss = &p->mult[size_t(p->m) * n3 * 2];
+  for (int dir = 0; dir < p->m; ++dir) {
+    const double* a = &p->mult[size_t(dir) * n3 * 2];
+    const double wd = p->w[dir];
+    for (int i = 0; i < n3; ++i) loss[2 * i] += wd * a[2 * i] * a[2 * i + 1];
+  }
+  for (int i = 0; i < n3; ++i) loss[2 * i + 1] = 1.0;
+  p->wext.assign(p->w.begin(), p->w.end());
+  p->wext.push_back(-1.0);
+}
+
+bool build_gram_inverse(bz_plan* p) {
+  const int n = p->n;
+  double G[25] = {};
+  for (int i1 = 0; i1 < n; ++i1)
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i3 = 0; i3 < n; ++i3) {
+        const double v1 = (i1 - n / 2) * p->dv, v2 = (i2 - n / 2) * p->dv, v3 = (i3 - n / 2) * p->dv;
+        const double c[5] = {1.0, v1, v2, v3, v1 * v1 + v2 * v2 + v3 * v3};
+        for (int a = 0; a < 5; ++a)
+          for (int b = 0; b < 5; ++b) G[5 * a + b] += c[a] * c[b];
+      }
+  return spd_inverse5(G, p->ginv);
+}
+
+void layout(bz_plan* p) {
+  const size_t n3 = size_t(p->n) * p->n * p->n;
+  const size_t es = p->fp32 ? 4 : 8;
+  p->table_mult_bytes = align256(size_t(p->m1) * n3 * 2 * es);
+  p->table_w_off = p->table_mult_bytes;
+  p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
+  const int acc_chunks = p->transform == BZ_XF_FUSED ? p->chunks : 1;
+  p->ws.fh_cell = align256(n3 * 2 * es);
+  p->ws.y_cell = align256(n3 * 2 * es);
+  p->ws.acc_cell = align256(n3 * es * acc_chunks);
+  p->ws_fixed = 0;
+  p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell;
+}
+
+}  // namespace
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+int32_t bz_abi_version(void) { return BZ_ABI_VERSION; }
+
+const char* bz_last_error(void) { return bz::last_error(); }
+
+bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
+  clear_error();
+  if (!desc || !out) return fail(BZ_ERR_ARG, "bz_plan_create: null argument");
+  *out = nullptr;
+  const bz_plan_desc& d = *desc;
+  if (!(d.n == 16 || d.n == 24 || d.n == 32 || d.n == 48))
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: n=%d not in {16,24,32,48}", d.n);
+  if (!(d.L > 0.0) || !std::isfinite(d.L)) return fail(BZ_ERR_ARG, "bz_plan_create: L must be > 0");
+  const double rmax = 4.0 * d.L / (3.0 + std::sqrt(2.0));
+  const double R = d.R > 0.0 ? d.R : (std::sqrt(2.0) - 1.0) * d.L;
+  if (!(R <= rmax * (1.0 + 1e-12)))
+    return fail(BZ_ERR_ARG, "bz_plan_create: R=%.17g exceeds the non-overlap bound 4L/(3+sqrt2)=%.17g", R, rmax);
+  if (!(d.gamma >= 0.0 && d.gamma <= 1.0)) return fail(BZ_ERR_ARG, "bz_plan_create: gamma must be in [0,1]");
+  if (!(d.kernel_c > 0.0) || !std::isfinite(d.kernel_c)) return fail(BZ_ERR_ARG, "bz_plan_create: kernel_c must be > 0");
+  if (d.m < 1 || d.m > 512) return fail(BZ_ERR_ARG, "bz_plan_create: m=%d not in 1..512", d.m);
+  if (d.precision != BZ_FP32 && d.precision != BZ_FP64) return fail(BZ_ERR_ARG, "bz_plan_create: bad precision");
+  if (d.transform < BZ_XF_AUTO || d.transform > BZ_XF_PLAIN) return fail(BZ_ERR_ARG, "bz_plan_create: bad transform");
+  if (d.max_cells < 1) return fail(BZ_ERR_ARG, "bz_plan_create: max_cells must be >= 1");
+  if (d.chunks < 0 || d.chunks > d.m + 1) return fail(BZ_ERR_ARG, "bz_plan_create: chunks must be in 0..m+1");
+
+  bz_plan* p = new bz_plan();
+  p->d = d;
+  p->d.dirs = nullptr;
+  p->d.weights = nullptr;
+  p->n = d.n;
+  p->m = d.m;
+  p->m1 = d.m + 1;
+  p->L = d.L;
+  p->R = R;
+  p->d.R = R;
+  p->gamma = d.gamma;
+  p->C = d.kernel_c;
+  p->dv = 2.0 * d.L / d.n;
+  p->fp32 = d.precision == BZ_FP32;
+  p->project = d.project ? 1 : 0;
+  switch (d.dir_kind) {
+    case BZ_DIRS_EXPLICIT:
+      if (!d.dirs || !d.weights) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: explicit rule needs dirs and weights"); }
+      p->dirs.assign(d.dirs, d.dirs + 3 * d.m);
+      p->w.assign(d.weights, d.weights + d.m);
+      break;
+    case BZ_DIRS_ICOSA6:
+      if (d.m != 6) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: ICOSA6 needs m=6"); }
+      rule_icosa6(p->dirs, p->w);
+      break;
+    case BZ_DIRS_PRODUCT:
+      if (d.a1 < 1 || d.a2 < 1 || d.a1 * d.a2 != d.m) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: PRODUCT needs a1*a2 == m"); }
+      rule_product(d.a1, d.a2, p->dirs, p->w);
+      break;
+    case BZ_DIRS_SPIRAL:
+      rule_spiral(d.m, p->dirs, p->w);
+      break;
+    default:
+      delete p;
+      return fail(BZ_ERR_ARG, "bz_plan_create: bad dir_kind %d", d.dir_kind);
+  }
+  double wsum = 0.0;
+  for (int i = 0; i < d.m; ++i) {
+    const double* e = &p->dirs[3 * i];
+    const double nrm = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!(std::fabs(nrm - 1.0) <= 1e-12)) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: direction %d is not a unit vector", i); }
+    if (!std::isfinite(p->w[i])) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: weight %d not finite", i); }
+    wsum += p->w[i];
+  }
+  if (!(std::fabs(wsum - 2.0 * kPi) <= 1e-12)) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: weights sum to %.17g, not 2*pi", wsum); }
+
+  const bool fused_ok = fused_supported(p->n, p->fp32);
+  if (d.transform == BZ_XF_FUSED && !fused_ok) {
+    delete p;
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel for n=%d precision=%s", d.n, p->fp32 ? "fp32" : "fp64");
+  }
+  p->transform = (d.transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
+  p->chunks = p->transform == BZ_XF_FUSED ? (d.chunks > 0 ? d.chunks : fused_default_chunks(p->n)) : 1;
+  if (p->chunks > p->m1) p->chunks = p->m1;
+  build_tables(p);
+  if (!build_gram_inverse(p)) { delete p; return fail(BZ_ERR_NUMERIC, "bz_plan_create: Gram matrix not positive definite"); }
+  layout(p);
+  *out = p;
+  return BZ_OK;
+}
+
+bz_status bz_plan_device_bytes(const bz_plan* p, size_t* tables, size_t* ws_fixed, size_t* ws_per_cell) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_plan_device_bytes: null plan");
+  if (tables) *tables = p->tables_bytes;
+  if (ws_fixed) *ws_fixed = p->ws_fixed;
+  if (ws_per_cell) *ws_per_cell = p->ws_per_cell;
+  return BZ_OK;
+}
+
+bz_status bz_plan_bind(bz_plan* p, void* tables_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p || !tables_dev || !ws_dev) return fail(BZ_ERR_ARG, "bz_plan_bind: null argument");
+  if ((uintptr_t(tables_dev) & 255) || (uintptr_t(ws_dev) & 255))
+    return fail(BZ_ERR_ARG, "bz_plan_bind: buffers must be 256-byte aligned");
+  if (ws_bytes < p->ws_fixed + p->ws_per_cell)
+    return fail(BZ_ERR_NOMEM, "bz_plan_bind: workspace %zu bytes < one cell (%zu)", ws_bytes, p->ws_fixed + p->ws_per_cell);
+  const size_t cap = (ws_bytes - p->ws_fixed) / p->ws_per_cell;
+  p->capacity = int(std::min<size_t>(cap, size_t(1) << 30));
+  p->ws.fh_off = p->ws_fixed;
+  p->ws.y_off = p->ws.fh_off + size_t(p->capacity) * p->ws.fh_cell;
+  p->ws.acc_off = p->ws.y_off + size_t(p->capacity) * p->ws.y_cell;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n3 = size_t(p->n) * p->n * p->n;
+  std::vector<unsigned char> host(p->tables_bytes, 0);
+  if (p->fp32) {
+    float* m = reinterpret_cast<float*>(host.data());
+    for (size_t i = 0; i < size_t(p->m1) * n3 * 2; ++i) m[i] = float(p->mult[i]);
+    float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
+    for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
+  } else {
+    std::memcpy(host.data(), p->mult.data(), size_t(p->m1) * n3 * 2 * 8);
+    std::memcpy(host.data() + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
+  }
+  hipError_t e = hipMemcpyAsync(tables_dev, host.data(), p->tables_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(BZ_ERR_DEVICE, "bz_plan_bind: table upload failed: %s", hipGetErrorString(e));
+  p->tables_dev = tables_dev;
+  p->ws_dev = ws_dev;
+  p->ws_bytes = ws_bytes;
+  return BZ_OK;
+}
+
+bz_status bz_plan_destroy(bz_plan* p) {
+  clear_error();
+  if (!p) return BZ_OK;
+  for (auto& e : p->evs) (void)hipEventDestroy(e);
+  delete p;
+  return BZ_OK;
+}
+
+bz_status bz_plan_capacity(const bz_plan* p, int32_t* cells) {
+  clear_error();
+  if (!p || !cells) return fail(BZ_ERR_ARG, "bz_plan_capacity: null argument");
+  if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_plan_capacity: plan not bound");
+  *cells = p->capacity;
+  return BZ_OK;
+}
+
+bz_status bz_plan_transform(const bz_plan* p, int32_t* transform) {
+  clear_error();
+  if (!p || !transform) return fail(BZ_ERR_ARG, "bz_plan_transform: null argument");
+  *transform = p->transform;
+  return BZ_OK;
+}
+
+bz_status bz_plan_get_rule(const bz_plan* p, double* dirs, double* weights) {
+  clear_error();
+  if (!p || !dirs || !weights) return fail(BZ_ERR_ARG, "bz_plan_get_rule: null argument");
+  std::memcpy(dirs, p->dirs.data(), sizeof(double) * 3 * p->m);
+  std::memcpy(weights, p->w.data(), sizeof(double) * p->m);
+  return BZ_OK;
+}
+
+bz_status bz_plan_get_multipliers(const bz_plan* p, int32_t pass, double* out) {
+  clear_error();
+  if (!p || !out) return fail(BZ_ERR_ARG, "bz_plan_get_multipliers: null argument");
+  if (pass < 0 || pass > p->m) return fail(BZ_ERR_ARG, "bz_plan_get_multipliers: pass %d not in 0..m", pass);
+  const size_t n3 = size_t(p->n) * p->n * p->n;
+  std::memcpy(out, &p->mult[size_t(pass) * n3 * 2], sizeof(double) * n3 * 2);
+  return BZ_OK;
+}
+
+bz_status bz_plan_set_timing(bz_plan* p, int32_t enable) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_plan_set_timing: null plan");
+  if (enable && !p->events_ready) {
+    p->evs.resize(4 * bz_plan::kTimingSlots);
+    for (auto& e : p->evs) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return fail(BZ_ERR_DEVICE, "bz_plan_set_timing: %s", hipGetErrorString(r));
+    }
+    p->events_ready = true;
+  }
+  p->timing = enable != 0;
+  p->timed_calls = 0;
+  return BZ_OK;
+}
+
+bz_status bz_plan_last_times(bz_plan* p, float* ms, int32_t n) {
+  clear_error();
+  if (!p || !ms || n < 1) return fail(BZ_ERR_ARG, "bz_plan_last_times: bad argument");
+  if (p->timed_calls < 1) return fail(BZ_ERR_STATE, "bz_plan_last_times: no timed call recorded");
+  const int calls = std::min(p->timed_calls, bz_plan::kTimingSlots);
+  double acc[4] = {0, 0, 0, 0};
+  for (int c = 0; c < calls; ++c) {
+    hipEvent_t* e = &p->evs[4 * c];
+    hipError_t r = hipEventSynchronize(e[3]);
+    if (r != hipSuccess) return fail(BZ_ERR_DEVICE, "bz_plan_last_times: %s", hipGetErrorString(r));
+    float t[4] = {};
+    (void)hipEventElapsedTime(&t[0], e[0], e[1]);
+    (void)hipEventElapsedTime(&t[1], e[1], e[2]);
+    (void)hipEventElapsedTime(&t[2], e[2], e[3]);
+    (void)hipEventElapsedTime(&t[3], e[0], e[3]);
+    for (int i = 0; i < 4; ++i) acc[i] += t[i];
+  }
+  for (int i = 0; i < n && i < 4; ++i) ms[i] = float(acc[i] / calls);
+  if (n > 4) ms[4] = float(calls);
+  p->timed_calls = 0;
+  return BZ_OK;
+}
+
+bz_status bz_collide_batch(const bz_plan* p, const void* f, int32_t f_dtype, const int32_t* idx,
+                           int32_t ncells, const int32_t* ncells_dev, void* q, int32_t flags,
+                           void* stream) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_collide_batch: null plan");
+  if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_collide_batch: plan not bound");
+  if (ncells < 0) return fail(BZ_ERR_ARG, "bz_collide_batch: ncells < 0");
+  if (ncells == 0) return BZ_OK;
+  if (!f || !q) return fail(BZ_ERR_ARG, "bz_collide_batch: null f or q");
+  if (f_dtype != BZ_FP32 && f_dtype != BZ_FP64) return fail(BZ_ERR_ARG, "bz_collide_batch: bad f_dtype");
+  if (flags & ~int32_t(BZ_SCATTER)) return fail(BZ_ERR_ARG, "bz_collide_batch: unknown flags");
+  if ((flags & BZ_SCATTER) && !idx) return fail(BZ_ERR_ARG, "bz_collide_batch: BZ_SCATTER needs idx");
+  if (ncells > p->capacity)
+    return fail(BZ_ERR_NOMEM, "bz_collide_batch: %d cells exceed the bound capacity %d", ncells, p->capacity);
+  return launch_collide(p, f, f_dtype == BZ_FP32, idx, ncells, ncells_dev, q,
+                        (flags & BZ_SCATTER) != 0, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+"""GPU parity of bz_collide_batch against the FP64 oracle, through the C ABI.
+
+Tolerance (per cell): ||Q_gpu - Q_ref||_2 / max(||Q_ref||_2, 0.05 ||loss_ref||_2)
+<= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path (FP32 transforms,
+multipliers, products and accumulation; FP64 projection).  The floor keeps
+near-equilibrium cells, where Q is a small difference of gain and loss, from
+dividing by ~0.  Conservation after projection: max_i |C_i Q| / sum |C_ij Q_j|
+<= 1e-12.
+"""
+import numpy as np
+import pytest
+
+import bz_inputs as gen
+from oracle import spectral
+from tests.gpu_util import cell_errors, lib_kwargs, oracle_cells, oracle_plan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def collider(n, cells, precision, rule="spiral", m=32, **kw):
+    import paper_2505_03360_amd as bz
+    args = dict(L=8.0, precision=precision)
+    args.update(lib_kwargs(rule, m))
+    args.update(kw)
+    return bz.Collider(n, cells, **args)
+
+
+def run(col, f_np, f_dtype=torch.float64, idx=None, scatter=False, ncells_dev=None, out=None):
+    f = torch.from_numpy(f_np).to("cuda", f_dtype).contiguous()
+    ii = None if idx is None else torch.as_tensor(idx, dtype=torch.int32, device="cuda")
+    q = col(f, idx=ii, scatter=scatter, ncells_dev=ncells_dev, out=out)
+    torch.cuda.synchronize()
+    return q.cpu().numpy()
+
+
+def label(*a):
+    print("case", *a, flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_single_cell_n16_icosa6(precision, tol):
+    """One cell, N=16 on [-8,8]^3, six icosahedral directions, hard spheres,
+    a seeded mix of two Maxwellians."""
+    import paper_2505_03360_amd as bz
+    label("n16 icosa6", precision)
+    f = gen.bimaxwellian_batch(1, 16, 8.0, seed=1)
+    col = collider(16, 1, precision, rule="icosa6", m=6)
+    q = run(col, f)
+    ref, loss = oracle_cells(f, oracle_plan(16, rule="icosa6", m=6))
+    err = cell_errors(q, ref, loss)
+    assert err.max() <= tol, err
+    assert spectral.moment_drift(q[0], 16, 8.0) <= 1e-12
+    if precision == bz.BZ_FP32:
+        assert col.transform == bz.BZ_XF_FUSED
+
+
+@pytest.mark.parametrize("precision,tol,transform", [(0, 1e-12, 2), (1, 1e-5, 1), (1, 1e-5, 2)])
+def test_ragged_gather_scatter_n16(precision, tol, transform):
+    """37 cells (a ragged count) gathered from 100 resident rows by an index
+    list, written back by scatter; untouched rows keep their sentinel."""
+    label("n16 ragged", precision, transform)
+    n = 16
+    allf = gen.bimaxwellian_batch(100, n, 8.0, seed=21)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(100, size=37, replace=False)).astype(np.int32)
+    col = collider(n, 40, precision, rule="spiral", m=8, transform=transform)
+    out = torch.full((100, n, n, n), 7.0, dtype=torch.float64, device="cuda")
+    q = run(col, allf, idx=idx, scatter=True, out=out)
+    ref, loss = oracle_cells(allf[idx], oracle_plan(n, rule="spiral", m=8))
+    err = cell_errors(q[idx], ref, loss)
+    assert err.max() <= tol, err
+    rest = np.setdiff1d(np.arange(100), idx)
+    assert np.all(q[rest] == 7.0)
+
+
+@pytest.mark.parametrize("precision,tol,cells", [(0, 1e-12, 3), (1, 1e-5, 6)])
+def test_n32_m32_shock_cells(precision, tol, cells):
+    """N=32, M=32 golden-spiral directions, Mott-Smith shock mixtures."""
+    label("n32 m32", precision)
+    f = gen.shock_batch(cells, 32, 8.0, seed=2)
+    col = collider(32, cells, precision)
+    q = run(col, f)
+    ref, loss = oracle_cells(f, oracle_plan(32))
+    err = cell_errors(q, ref, loss)
+    print("max err", err.max(), flush=True)
+    assert err.max() <= tol, err
+    for c in range(cells):
+        assert spectral.moment_drift(q[c], 32, 8.0) <= 1e-12
+
+
+def test_n32_full_batch_sampled():
+    """The benchmarked launch: 256 cells, N=32, M=32, FP32 fused + FP64
+    projection; sampled cells checked against the oracle, every cell
+    checked for conservation and finiteness."""
+    label("n32 full batch")
+    f = gen.shock_batch(256, 32, 8.0, seed=2)
+    col = collider(32, 256, 1)
+    q = run(col, f, f_dtype=torch.float64)
+    assert np.isfinite(q).all()
+    sample = [0, 77, 128, 200, 255]
+    ref, loss = oracle_cells(f[sample], oracle_plan(32))
+    err = cell_errors(q[sample], ref, loss)
+    assert err.max() <= 1e-5, err
+    drift = max(spectral.moment_drift(q[c], 32, 8.0) for c in range(0, 256, 15))
+    assert drift <= 1e-12
+
+
+@pytest.mark.parametrize("n,precision,tol", [(24, 1, 1e-5), (24, 0, 1e-12), (48, 1, 1e-5)])
+def test_radix3_sizes(n, precision, tol):
+    label("radix3", n, precision)
+    f = gen.bimaxwellian_batch(2, n, 8.0, seed=n)
+    col = collider(n, 2, precision, rule="spiral", m=8)
+    q = run(col, f)
+    ref, loss = oracle_cells(f, oracle_plan(n, rule="spiral", m=8))
+    err = cell_errors(q, ref, loss)
+    assert err.max() <= tol, err
+
+
+@pytest.mark.parametrize("gamma,transform", [(0.0, 1), (0.5, 2), (0.5, 1)])
+def test_vhs_exponents(gamma, transform):
+    label("gamma", gamma, transform)
+    f = gen.shock_batch(2, 16, 8.0, seed=3)
+    col = collider(16, 2, 1, rule="spiral", m=16, gamma=gamma, transform=transform)
+    q = run(col, f)
+    ref, loss = oracle_cells(f, oracle_plan(16, rule="spiral", m=16, gamma=gamma))
+    assert cell_errors(q, ref, loss).max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_raw_output_without_projection(precision):
+    label("raw", precision)
+    f = gen.bimaxwellian_batch(3, 16, 8.0, seed=4)
+    col = collider(16, 3, precision, rule="product44", m=16, project=0)
+    q = run(col, f, f_dtype=torch.float32 if precision else torch.float64)
+    fin = f.astype(np.float32).astype(np.float64) if precision else f
+    ref, loss = oracle_cells(fin, oracle_plan(16, rule="product44", m=16), project=False)
+    tol = 1e-5 if precision else 1e-12
+    assert cell_errors(q, ref, loss).max() <= tol
+
+
+@pytest.mark.parametrize("precision,transform", [(1, 1), (0, 2)])
+def test_batch_independence_bitwise(precision, transform):
+    """A cell's result does not depend on the rest of the batch."""
+    label("bitwise", precision, transform)
+    n = 32 if transform == 1 else 16
+    f = gen.shock_batch(9, n, 8.0, seed=8)
+    col = collider(n, 9, precision, rule="spiral", m=8, transform=transform)
+    q_all = run(col, f)
+    for c in (0, 4, 8):
+        q_one = run(col, f[c:c + 1])
+        assert np.array_equal(q_one[0], q_all[c])
+    q_rev = run(col, f[::-1].copy())
+    assert np.array_equal(q_rev[::-1], q_all)
+
+
+def test_device_count():
+    """ncells_dev limits the processed cells on the GPU."""
+    label("device count")
+    f = gen.bimaxwellian_batch(8, 16, 8.0, seed=9)
+    col = collider(16, 8, 1, rule="spiral", m=8)
+    cnt = torch.tensor([5], dtype=torch.int32, device="cuda")
+    out = torch.full((8, 16, 16, 16), -3.0, dtype=torch.float64, device="cuda")
+    q = run(col, f, ncells_dev=cnt, out=out)
+    full = run(col, f)
+    assert np.array_equal(q[:5], full[:5])
+    assert np.all(q[5:] == -3.0)
+
+
+def test_timing_and_errors():
+    import paper_2505_03360_amd as bz
+    col = collider(16, 4, 1, rule="spiral", m=8)
+    bz.bz_plan_set_timing(col.plan, True)
+    f = torch.from_numpy(gen.bimaxwellian_batch(4, 16, 8.0, seed=2)).cuda()
+    col(f)
+    ms = bz.bz_plan_last_times(col.plan)
+    assert ms[3] > 0 and all(x >= 0 for x in ms)
+    with pytest.raises(bz.BzError) as e:
+        col(torch.cat([f, f]))  # 8 cells > capacity 4
+    assert e.value.code == bz.BZ_ERR_NOMEM

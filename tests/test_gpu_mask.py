@@ -1,0 +1,100 @@
+"""GPU parity of bz_realizability_mask against the FP64 mask oracle: regime
+codes, the ordered list of Boltzmann cells and the four indicators must match
+bit for bit."""
+import numpy as np
+import pytest
+
+import bz_inputs as gen
+from oracle import mask as om
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def run_both(d, rho, ux, uy, T, eps, regime, l1=None, flags=None, mode=0):
+    import paper_2505_03360_amd as bz
+    print("case mask", d.nx, d.ny, mode, flush=True)
+    d.laplacian_u_mode = mode
+    cu = lambda a, dt=torch.float64: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    bd = bz.mask_desc(d.nx, d.ny, d.dx, d.dy, d.mu0, d.kappa0, d.eta0, d.eta1, d.delta0, mode)
+    rout, idx, counts, diag = bz.realizability_mask(bd, cu(rho), cu(ux), cu(uy), cu(T), cu(eps),
+                                                    cu(regime, torch.uint8), cu(l1),
+                                                    cu(flags, torch.uint8), with_diag=True)
+    torch.cuda.synchronize()
+    counts = counts.cpu().numpy()
+    g_out = rout.cpu().numpy()
+    g_idx = idx.cpu().numpy()[:counts[0]]
+    g_diag = diag.cpu().numpy()
+    o_out, o_idx, o_diag, o_bad = om.realizability_mask(d, rho, ux, uy, T, eps, regime, l1, flags)
+    return (g_out, g_idx, g_diag, counts), (o_out, o_idx, o_diag, o_bad)
+
+
+def assert_same(g, o):
+    (g_out, g_idx, g_diag, counts), (o_out, o_idx, o_diag, o_bad) = g, o
+    assert np.array_equal(g_out, o_out)
+    assert np.array_equal(g_idx, o_idx)
+    assert counts[0] == len(o_idx) and counts[1] == o_bad
+    same = (g_diag == o_diag) | (np.isnan(g_diag) & np.isnan(o_diag))
+    assert same.all(), np.argwhere(~same)[:5]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_mask_random_fields(mode):
+    nx, ny = 61, 47
+    rho, ux, uy, T = gen.random_macro_field(nx, ny, seed=13)
+    d = om.MaskDesc(nx=nx, ny=ny, dx=1.0 / nx, dy=1.0 / ny, eta0=1e-3)
+    eps = np.full((ny, nx), 2e-3)
+    lam = om.indicators(d, rho, ux, uy, T, eps)
+    d.eta1 = float(np.quantile(lam[3], 0.7))
+    rng = np.random.default_rng(4)
+    regime = rng.integers(0, 3, size=(ny, nx)).astype(np.uint8)
+    l1 = rng.uniform(0, 2e-4, size=(ny, nx))
+    d.delta0 = 1e-4
+    g, o = run_both(d, rho, ux, uy, T, eps, regime, l1=l1, mode=mode)
+    assert_same(g, o)
+    assert 0 < len(o[1]) < nx * ny
+
+
+def test_mask_bow_shock_128():
+    """128 x 128 bow-shock field, thresholds of the obstacle tests (eps=1e-4,
+    eta0=1e-3), eta1 at the 85th percentile of lambda_B, every cell starting
+    in the ES-BGK layer; repeated over moving-shock steps feeding the regimes
+    back."""
+    nx = ny = 128
+    rho, ux, uy, T = gen.bow_shock_field(nx, ny, step=0, seed=3)
+    d = om.MaskDesc(nx=nx, ny=ny, dx=1.0 / nx, dy=1.0 / ny, eta0=1e-3, delta0=1e-4)
+    eps = np.full((ny, nx), 1e-4)
+    lam = om.indicators(d, rho, ux, uy, T, eps)
+    d.eta1 = float(np.quantile(lam[3], 0.85))
+    regime = np.ones((ny, nx), np.uint8)
+    for step in range(3):
+        rho, ux, uy, T = gen.bow_shock_field(nx, ny, step=step, seed=3)
+        g, o = run_both(d, rho, ux, uy, T, eps, regime)
+        assert_same(g, o)
+        assert om.margin_cells(d, om.indicators(d, rho, ux, uy, T, eps)) == 0
+        regime = o[0]
+    frac = len(o[1]) / (nx * ny)
+    assert 0.05 < frac < 0.3
+
+
+def test_mask_flags_and_invalid_cells():
+    nx, ny = 33, 17
+    rho, ux, uy, T = gen.random_macro_field(nx, ny, seed=7)
+    rho[3, 4] = -1.0
+    T[10, 20] = np.nan
+    d = om.MaskDesc(nx=nx, ny=ny, dx=0.1, dy=0.1, eta0=1e-3, eta1=1e-5)
+    eps = np.full((ny, nx), 1e-3)
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0, :5] = om.FORCE_BOLTZMANN
+    flags[5, 5:9] = om.SOLID
+    regime = np.full((ny, nx), 1, np.uint8)
+    regime[12, :] = 255
+    g, o = run_both(d, rho, ux, uy, T, eps, regime, flags=flags)
+    assert_same(g, o)
+    assert g[3][1] >= 2

@@ -1,0 +1,107 @@
+"""Host-side checks of the HIP library that need no GPU: the shared object
+loads and exports every entry point include/bz.h declares, descriptors are
+validated, and the plan's FP64 direction rules and multiplier tables (the
+library's own special functions) agree with the oracle's independent ones."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_03360_amd as bz
+from oracle import directions, spectral
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(bz_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = bz.lib()
+    syms = header_symbols()
+    assert "bz_collide_batch" in syms and "bz_realizability_mask" in syms
+    for s in sorted(syms):
+        assert hasattr(L, s), s
+    assert bz.bz_abi_version() == 1
+    declared = {name for name, _, _ in bz.SIGNATURES}
+    assert syms <= declared | {"bz_serve_submit", "bz_serve_poll", "bz_server_create",
+                               "bz_server_destroy", "bz_server_stats"} or syms <= declared
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=20), bz.BZ_ERR_UNSUPPORTED),
+    (dict(R=7.3), bz.BZ_ERR_ARG),
+    (dict(gamma=1.5), bz.BZ_ERR_ARG),
+    (dict(m=7, dir_kind=bz.BZ_DIRS_ICOSA6), bz.BZ_ERR_ARG),
+    (dict(m=16, dir_kind=bz.BZ_DIRS_PRODUCT, a1=4, a2=3), bz.BZ_ERR_ARG),
+    (dict(max_cells=0), bz.BZ_ERR_ARG),
+    (dict(n=24, transform=bz.BZ_XF_FUSED), bz.BZ_ERR_UNSUPPORTED),
+    (dict(precision=bz.BZ_FP64, transform=bz.BZ_XF_FUSED), bz.BZ_ERR_UNSUPPORTED),
+])
+def test_plan_validation(kw, code):
+    args = dict(n=16, L=8.0, m=6, dir_kind=bz.BZ_DIRS_ICOSA6)
+    args.update(kw)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_create(bz.make_plan_desc(**args))
+    assert e.value.code == code
+    assert bz.bz_last_error() != ""
+
+
+def test_explicit_rule_weight_sum_checked():
+    d, w = directions.spiral(8)
+    with pytest.raises(bz.BzError):
+        bz.bz_plan_create(bz.make_plan_desc(n=16, dirs=d, weights=w * 1.001))
+    with pytest.raises(bz.BzError):
+        bz.bz_plan_create(bz.make_plan_desc(n=16, dirs=d * 1.01, weights=w))
+
+
+@pytest.mark.parametrize("kind,m,a", [(bz.BZ_DIRS_ICOSA6, 6, (0, 0)), (bz.BZ_DIRS_PRODUCT, 16, (4, 4)),
+                                      (bz.BZ_DIRS_SPIRAL, 32, (0, 0))])
+def test_direction_rules_match_oracle(kind, m, a):
+    p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=m, dir_kind=kind, a1=a[0], a2=a[1]))
+    d, w = bz.bz_plan_get_rule(p, m)
+    bz.bz_plan_destroy(p)
+    ref = {bz.BZ_DIRS_ICOSA6: directions.icosa6, bz.BZ_DIRS_PRODUCT: lambda: directions.product(4, 4),
+           bz.BZ_DIRS_SPIRAL: lambda: directions.spiral(32)}[kind]()
+    assert np.abs(d - ref[0]).max() <= 1e-15 and np.abs(w - ref[1]).max() <= 1e-15
+
+
+@pytest.mark.parametrize("n,gamma,R", [(16, 1.0, 0.0), (16, 0.0, 5.0), (24, 0.5, 0.0), (32, 1.0, 7.2)])
+def test_multipliers_match_oracle(n, gamma, R):
+    L = 8.0
+    p = bz.bz_plan_create(bz.make_plan_desc(n=n, L=L, R=R, gamma=gamma, m=32, dir_kind=bz.BZ_DIRS_SPIRAL))
+    d, w = directions.spiral(32)
+    plan = spectral.Plan(n, L, R if R > 0 else spectral.default_R(L), gamma, 4.0, d, w)
+    for pi in (0, 7, 31):
+        a, ap = bz.bz_plan_get_multipliers(p, n, pi)
+        ra, rap = spectral.multipliers(plan, pi)
+        assert np.abs(a - ra).max() <= 1e-12 * np.abs(ra).max(), pi
+        assert np.abs(ap - rap).max() <= 1e-12 * np.abs(rap).max(), pi
+    bl, one = bz.bz_plan_get_multipliers(p, n, 32)
+    assert np.abs(bl - spectral.bhat_m(plan)).max() <= 1e-12 * np.abs(bl).max()
+    assert np.all(one == 1.0)
+    bz.bz_plan_destroy(p)
+
+
+def test_device_bytes_scale():
+    p = bz.bz_plan_create(bz.make_plan_desc(n=32, m=32, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP32))
+    t, fixed, per = bz.bz_plan_device_bytes(p)
+    assert t >= 33 * 32 ** 3 * 8
+    assert per >= 32 ** 3 * (8 + 4)
+    assert bz.bz_plan_transform(p) == bz.BZ_XF_FUSED
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_capacity(p)
+    assert e.value.code == bz.BZ_ERR_STATE
+    bz.bz_plan_destroy(p)
+    p = bz.bz_plan_create(bz.make_plan_desc(n=32, m=32, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP64))
+    assert bz.bz_plan_transform(p) == bz.BZ_XF_PLAIN
+    bz.bz_plan_destroy(p)

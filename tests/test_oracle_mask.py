@@ -91,7 +91,7 @@ def test_p12_uniform_state_branches():
     flags[2, 2] = om.SOLID | om.FORCE_BOLTZMANN
     out = om.regime_update(d, lam, regime, flags=flags)
     assert out[0, 0] == 2 and out[1, 1] == 255 and out[2, 2] == 255
-    o2, idx, diag = om.realizability_mask(d, one, 0 * one, 0 * one, one, 1e-2 * one, regime, flags=flags)
+    o2, idx, diag, nbad = om.realizability_mask(d, one, 0 * one, 0 * one, one, 1e-2 * one, regime, flags=flags)
     assert list(idx) == [0]
 
 
@@ -139,7 +139,7 @@ def test_compaction_ascending_and_margin():
     d.eta1 = float(np.quantile(lam[3], 0.8))
     d.eta1 *= 1.0 + 1e-9
     regime = np.ones((ny, nx), np.uint8)
-    out, idx, diag = om.realizability_mask(d, rho, ux, uy, T, eps, regime)
+    out, idx, diag, nbad = om.realizability_mask(d, rho, ux, uy, T, eps, regime)
     assert np.all(np.diff(idx) > 0)
     assert len(idx) == int((out == 2).sum())
     assert om.margin_cells(d, lam) == 0
