@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the collision evaluation of a cell batch runs on a "
@@ -121,6 +123,14 @@ def main():
     q32 = out.cpu().numpy()
     q64 = out64.cpu().numpy()
     diff = np.linalg.norm((q32 - q64).reshape(CELLS, -1), axis=1) / np.linalg.norm(q64.reshape(CELLS, -1), axis=1)
+
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     total_flops, kern_flops = algorithmic_flops(N, M)
     kern_s = stage_ms[1] * 1e-3

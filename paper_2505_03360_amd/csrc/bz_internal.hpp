@@ -41,7 +41,8 @@ struct bz_plan {
   // FP64 host tables in device layout [p][k2][k3][k1] x (a, a'), p < m1;
   // pass p = m carries (Bhat_M, 1) with weight -1.
   std::vector<double> mult;
-  std::vector<double> wext;     // [m1]
+  std::vector<double> wext;     // [m1] device weights: w_p, then the loss scale
+  std::vector<double> pscale;   // [m1] per-pass balance factor of the packed transform
   double ginv[25] = {};         // (C C^T)^-1 of the five invariants
   size_t table_mult_bytes = 0, table_w_off = 0, tables_bytes = 0;
   size_t ws_fixed = 0, ws_per_cell = 0;

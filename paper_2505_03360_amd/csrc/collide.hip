@@ -1,15 +1,19 @@
 // Kernels of the fast spectral collision operator (Sec. 4.4.1) for gfx950.
 //
-// Per cell, with fhat = DFT(f)/n^3 (Nyquist zeroed) and, for every pass p of
-// the direction list extended by the loss pass:
-//   X_p = (alpha_p + i alpha'_p) * fhat         (both multipliers are real and even)
-//   Y_p = IDFT(X_p) = IDFT(alpha_p fhat) + i IDFT(alpha'_p fhat)
+// Per cell, with fhat = DFT(f)/n^3 and, for every direction p:
+//   X_p = (s_p alpha_p + i alpha'_p / s_p) * fhat   (real, even multipliers,
+//                                                    zero on the Nyquist planes)
+//   Y_p = IDFT(X_p) = s_p IDFT(alpha_p fhat) + i IDFT(alpha'_p fhat) / s_p
 //   acc += w_p * Re(Y_p) * Im(Y_p)
 // Both inverse transforms of a direction are real, so one complex transform
-// carries the pair.  The loss pass has multipliers (Bhat_M, 1) and weight -1,
-// which adds -IDFT(Bhat_M fhat) * IDFT(fhat).  The result kernel_c * acc is
-// Q(f,f); the FP64 projection kernel removes its component along the five
-// collision invariants.
+// carries the pair; the balance factor s_p leaves the product unchanged and
+// equalises the rounding of the two parts.  The loss pass carries
+// X = (Bhat_M / sL + i sL [Nyquist]) fhat, i.e. Y = Lambda/sL + i sL fNyq with
+// fNyq the Nyquist-mode part of f, and adds -(sL f - Im Y) Re Y =
+// -(f - fNyq) Lambda = -fN Lambda, the loss term of the truncated series,
+// formed with the exact input f.  The result kernel_c * acc is Q(f,f); the
+// FP64 projection kernel removes its component along the five collision
+// invariants.
 //
 // Layouts (per cell, n^3 entries): f and q [i1][i2][i3]; fhat, multipliers
 // [k2][k3][k1] (k1 fastest, so that stage-A pencils along k3 are read with
@@ -54,6 +58,7 @@ struct PlainArgs {
   const T* w;         // [pass]
   int pass;
   int first;
+  int loss;  // this pass is the loss pass (the last one)
 };
 
 // ------------------------------------------------------------------ forward
@@ -100,8 +105,8 @@ __global__ __launch_bounds__(256) void k_fwd2(PlainArgs<T> a) {
   for (int k2 = 0; k2 < N; ++k2) y[k2 * N] = x[k2];
 }
 
-// pass 3: pencils along i3, thread (cell, k2, k1); scale by n^-3, zero the
-// Nyquist modes, write fhat[cell][k2][k3][k1]
+// pass 3: pencils along i3, thread (cell, k2, k1); scale by n^-3 and
+// write fhat[cell][k2][k3][k1] with the Nyquist modes kept (the loss pass uses them)
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_fwd3(PlainArgs<T> a) {
   const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -115,13 +120,14 @@ __global__ __launch_bounds__(256) void k_fwd3(PlainArgs<T> a) {
   for (int i3 = 0; i3 < N; ++i3) x[i3] = y[i3];
   bzk::fft<N, -1>(x);
   const T scale = T(1.0 / (double(N) * N * N));
-  const bool nyq12 = (k1 == N / 2) || (k2 == N / 2);
   cx<T>* fh = a.fh + c * a.fh_stride + size_t(k2) * N * N + k1;
 #pragma unroll
-  for (int k3 = 0; k3 < N; ++k3) {
-    const bool z = nyq12 || (k3 == N / 2);
-    fh[size_t(k3) * N] = z ? cx<T>{T(0), T(0)} : cx<T>{x[k3].x * scale, x[k3].y * scale};
-  }
+  for (int k3 = 0; k3 < N; ++k3) fh[size_t(k3) * N] = cx<T>{x[k3].x * scale, x[k3].y * scale};
+}
+
+template <typename T>
+__device__ __forceinline__ T load_f(const void* f, int f_fp32, size_t i) {
+  return f_fp32 ? T(static_cast<const float*>(f)[i]) : T(static_cast<const double*>(f)[i]);
 }
 
 // ------------------------------------------------------------------ plain passes
@@ -182,7 +188,15 @@ __global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
   bzk::fft<N, 1>(x);
   const T wp = a.w[a.pass];
   T* acc = a.acc + c * a.acc_stride + size_t(j2) * N + j3;
-  if (a.first) {
+  if (a.loss) {
+    const long row = a.idx ? long(a.idx[c]) : long(c);
+    const size_t fb = size_t(row) * N * N * N + size_t(j2) * N + j3;
+#pragma unroll
+    for (int j1 = 0; j1 < N; ++j1) {
+      const T fj = load_f<T>(a.f, a.f_fp32, fb + size_t(j1) * N * N);
+      acc[size_t(j1) * N * N] -= (wp * fj - x[j1].y) * x[j1].x;
+    }
+  } else if (a.first) {
 #pragma unroll
     for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] = wp * x[j1].x * x[j1].y;
   } else {
@@ -195,6 +209,9 @@ __global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
 struct FusedArgs {
   int ncells;
   const int32_t* ncells_dev;
+  const void* f;
+  int f_fp32;
+  const int32_t* idx;
   const cx<float>* fh;
   size_t fh_stride;
   float* acc;
@@ -213,9 +230,105 @@ struct FusedArgs {
 //            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
 // LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
 // lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
+template <int N, int S, bool LOSS>
+__device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, const cx<float>* fhc,
+                                           long row, int p, int t, float (&acc)[S][N]) {
+  constexpr int T = N * N / S;
+  constexpr int W = N / S;
+  constexpr int AB = W + 1;
+  const int tb_k1 = t / W, tl = t % W;  // stage B: k1, j3 % W; stage C: j2, j3 % W
+  const cx<float>* mp = a.mult + size_t(p) * N * N * N;
+  const float wp = a.w[p];
+  // stage A: each pencil is loaded in two halves (bounded registers in
+  // flight), transformed, and its slice-0 outputs go to LDS at once; the
+  // other slices stay in registers until their turn.
+  cx<float> rest[S > 1 ? S : 1][S > 1 ? N - W : 1];
+  __syncthreads();  // LDS free: the previous pass's stage C has read it
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int P = q * T + t;
+    const int k1 = P % N, k2 = P / N;
+    const size_t off = size_t(k2) * N * N + k1;
+    // Opaque per-pass bases: keeps the compiler from hoisting the n
+    // per-element addresses out of the pass loop (they would occupy 2n
+    // registers); loads then use base + immediate offsets.
+    const cx<float>* fb = fhc + off;
+    const cx<float>* mb = mp + off;
+    asm volatile("" : "+v"(fb), "+v"(mb));
+    cx<float> x[N];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+        const cx<float> F = fb[k3 * N];
+        const cx<float> M = mb[k3 * N];
+        x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    bzk::fft<N, 1>(x);
+#pragma unroll
+    for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = x[j];
+    if constexpr (S > 1) {
+#pragma unroll
+      for (int j = W; j < N; ++j) rest[q][j - W] = x[j];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (s > 0) {
+      __syncthreads();  // stage C of the previous slice has read the LDS
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const int P = q * T + t;
+        const int k1 = P % N, k2 = P / N;
+#pragma unroll
+        for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = rest[q][(s - 1) * W + j];
+      }
+    }
+    __syncthreads();
+    cx<float> rb[N];
+#pragma unroll
+    for (int k2 = 0; k2 < N; ++k2) rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
+    bzk::fft<N, 1>(rb);
+    __syncthreads();
+#pragma unroll
+    for (int j2 = 0; j2 < N; ++j2) lds[(j2 * N + tb_k1) * W + tl] = rb[j2];
+    __syncthreads();
+    cx<float> rc[N];
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
+    bzk::fft<N, 1>(rc);
+    if constexpr (LOSS) {
+      // acc -= (sL f - Im) Re with the exact input f
+      const size_t fo = size_t(row) * N * N * N + size_t(tb_k1) * N + s * W + tl;
+      if (a.f_fp32) {
+        const float* fp = static_cast<const float*>(a.f) + fo;
+#pragma unroll
+        for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * fp[j1 * N * N] - rc[j1].y) * rc[j1].x;
+      } else {
+        const double* fp = static_cast<const double*>(a.f) + fo;
+#pragma unroll
+        for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * float(fp[j1 * N * N]) - rc[j1].y) * rc[j1].x;
+      }
+    } else {
+#pragma unroll
+      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += wp * rc[j1].x * rc[j1].y;
+    }
+  }
+}
+
+// N^2/S threads; S j3-slices of width W = N/S.
+//   stage A: thread t owns pencils P = a*T + t (a < S) along k3 at
+//            (k1, k2) = (P % N, P / N);
+//   stage B: thread t owns, in every slice, the pencil along k2 at
+//            (k1, j3) = (t / W, s*W + t % W);
+//   stage C: thread t owns, in every slice, the pencil along k1 at
+//            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
+// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
+// lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
 template <int N, int S>
 __global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
-  constexpr int T = N * N / S;
   constexpr int W = N / S;
   constexpr int AB = W + 1;
   __shared__ cx<float> lds[N * N * AB];
@@ -225,60 +338,18 @@ __global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
   const int p0 = int((long(chunk) * a.m1) / a.chunks);
   const int p1 = int((long(chunk + 1) * a.m1) / a.chunks);
   const int t = threadIdx.x;
-  const int tb_k1 = t / W, tl = t % W;  // stage B: k1, j3 % W; stage C: j2, j3 % W
+  const long row = a.idx ? long(a.idx[cell]) : long(cell);
   const cx<float>* fhc = a.fh + cell * a.fh_stride;
   float acc[S][N];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[s][j] = 0.0f;
-
-  for (int p = p0; p < p1; ++p) {
-    const cx<float>* mp = a.mult + size_t(p) * N * N * N;
-    const float wp = a.w[p];
-    cx<float> ra[S][N];
-#pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const int P = q * T + t;
-      const int k1 = P % N, k2 = P / N;
-      const size_t off = size_t(k2) * N * N + k1;
-#pragma unroll
-      for (int k3 = 0; k3 < N; ++k3) {
-        const cx<float> F = fhc[off + size_t(k3) * N];
-        const cx<float> M = mp[off + size_t(k3) * N];
-        ra[q][k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
-      }
-      bzk::fft<N, 1>(ra[q]);
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < S; ++q) {
-        const int P = q * T + t;
-        const int k1 = P % N, k2 = P / N;
-#pragma unroll
-        for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = ra[q][s * W + j];
-      }
-      __syncthreads();
-      cx<float> rb[N];
-#pragma unroll
-      for (int k2 = 0; k2 < N; ++k2) rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
-      bzk::fft<N, 1>(rb);
-      __syncthreads();
-#pragma unroll
-      for (int j2 = 0; j2 < N; ++j2) lds[(j2 * N + tb_k1) * W + tl] = rb[j2];
-      __syncthreads();
-      cx<float> rc[N];
-#pragma unroll
-      for (int k1 = 0; k1 < N; ++k1) rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
-      bzk::fft<N, 1>(rc);
-#pragma unroll
-      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += wp * rc[j1].x * rc[j1].y;
-    }
-  }
+  const int gain_end = p1 < a.m1 - 1 ? p1 : a.m1 - 1;
+  for (int p = p0; p < gain_end; ++p) fused_pass<N, S, false>(a, lds, fhc, row, p, t, acc);
+  if (p1 == a.m1) fused_pass<N, S, true>(a, lds, fhc, row, a.m1 - 1, t, acc);
   float* out = a.acc + cell * a.acc_stride + size_t(chunk) * N * N * N;
-  const int j2 = tb_k1;
+  const int j2 = t / W, tl = t % W;
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -386,6 +457,7 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   for (int p = 0; p < m1; ++p) {
     a.pass = p;
     a.first = p == 0;
+    a.loss = p == m1 - 1;
     hipLaunchKernelGGL((k_dirA<T, N>), grid, block, 0, s, a);
     hipLaunchKernelGGL((k_dirB<T, N>), grid, block, 0, s, a);
     hipLaunchKernelGGL((k_dirC<T, N>), grid, block, 0, s, a);
@@ -483,6 +555,9 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
       FusedArgs fa{};
       fa.ncells = ncells;
       fa.ncells_dev = ncells_dev;
+      fa.f = f;
+      fa.f_fp32 = f_fp32;
+      fa.idx = idx;
       fa.fh = a.fh;
       fa.fh_stride = a.fh_stride;
       fa.acc = a.acc;

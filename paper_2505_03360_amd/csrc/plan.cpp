@@ -208,8 +208,44 @@ void build_tables(bz_plan* p) {
     for (int i = 0; i < n3; ++i) loss[2 * i] += wd * a[2 * i] * a[2 * i + 1];
   }
   for (int i = 0; i < n3; ++i) loss[2 * i + 1] = 1.0;
+  // Balance factors of the packed transforms.  Y = IDFT((a s + i a'/s) fhat)
+  // carries s A and A'/s, whose product is A A' for any s; s equalises the
+  // two parts so that FP32 rounding of the transform hits both alike.  The
+  // loss pass packs Lambda/sL with sL fNyq (the Nyquist part of f):
+  // fN Lambda = (f - fNyq) Lambda is then formed with the exact input f,
+  // sL = sqrt(Bhat_M(0)) (Lambda/f is scale free, so one sL fits all cells).
+  p->pscale.assign(p->m1, 1.0);
+  for (int dir = 0; dir < p->m; ++dir) {
+    const double* a = &p->mult[size_t(dir) * n3 * 2];
+    double ma = 0.0, mb = 0.0;
+    for (int i = 0; i < n3; ++i) {
+      ma = std::max(ma, std::fabs(a[2 * i]));
+      mb = std::max(mb, std::fabs(a[2 * i + 1]));
+    }
+    p->pscale[dir] = (ma > 0.0 && mb > 0.0) ? std::sqrt(mb / ma) : 1.0;
+  }
+  p->pscale[p->m] = std::sqrt(std::fabs(loss[0]) > 0.0 ? std::fabs(loss[0]) : 1.0);
   p->wext.assign(p->w.begin(), p->w.end());
-  p->wext.push_back(-1.0);
+  p->wext.push_back(p->pscale[p->m]);
+}
+
+// Device form of pass `pass` at table index i ([k2][k3][k1] order): gain
+// passes (a s, a'/s), zero on the Nyquist planes; the loss pass
+// (Bhat_M/sL, sL [k on a Nyquist plane]).
+void device_multiplier(const bz_plan* p, int pass, size_t i, double& re, double& im) {
+  const int n = p->n;
+  const size_t n3 = size_t(n) * n * n;
+  const int k1 = int(i % n), k3 = int((i / n) % n), k2 = int(i / (size_t(n) * n));
+  const bool nyq = k1 == n / 2 || k2 == n / 2 || k3 == n / 2;
+  const double* a = &p->mult[size_t(pass) * n3 * 2];
+  const double s = p->pscale[pass];
+  if (pass < p->m) {
+    re = nyq ? 0.0 : a[2 * i] * s;
+    im = nyq ? 0.0 : a[2 * i + 1] / s;
+  } else {
+    re = nyq ? 0.0 : a[2 * i] / s;
+    im = nyq ? s : 0.0;
+  }
 }
 
 bool build_gram_inverse(bz_plan* p) {
@@ -356,13 +392,20 @@ bz_status bz_plan_bind(bz_plan* p, void* tables_dev, void* ws_dev, size_t ws_byt
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t n3 = size_t(p->n) * p->n * p->n;
   std::vector<unsigned char> host(p->tables_bytes, 0);
+  const size_t entries = size_t(p->m1) * n3;
   if (p->fp32) {
     float* m = reinterpret_cast<float*>(host.data());
-    for (size_t i = 0; i < size_t(p->m1) * n3 * 2; ++i) m[i] = float(p->mult[i]);
+    for (size_t e = 0; e < entries; ++e) {
+      double re, im;
+      device_multiplier(p, int(e / n3), e % n3, re, im);
+      m[2 * e] = float(re);
+      m[2 * e + 1] = float(im);
+    }
     float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
     for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
   } else {
-    std::memcpy(host.data(), p->mult.data(), size_t(p->m1) * n3 * 2 * 8);
+    double* m = reinterpret_cast<double*>(host.data());
+    for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
     std::memcpy(host.data() + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
   }
   hipError_t e = hipMemcpyAsync(tables_dev, host.data(), p->tables_bytes, hipMemcpyHostToDevice, s);
