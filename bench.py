@@ -65,6 +65,83 @@ def cpu_baseline(f, budget_s: float = 15.0):
             "sample": f"{done} cells of the {CELLS}-cell N=32 M=32 batch, FP64 naive-DFT oracle + projection, {dt:.1f} s"}
 
 
+def serving_run(seconds: float, seed: int = 5):
+    """Serving workload: 4 client threads, each keeping two requests in flight;
+    a request has N drawn from {16, 24, 32, 48}, M = 32, cells ~ Poisson(512)
+    clipped to [16, 4096], FP32 input, FP32 evaluation + FP64 projection;
+    16 GiB arena so that admission by memory binds.  Latency = done - submit."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    sizes = (16, 24, 32, 48)
+    pool = {}
+    for n in sizes:
+        base = torch.from_numpy(gen.bimaxwellian_batch(32, n, L, seed=seed + n)).float().cuda()
+        pool[n] = base.repeat(4096 // 32, 1, 1, 1).contiguous()
+    srv = bz.Server(arena_bytes=16 << 30, max_inflight=16, n_streams=4, max_queue=1 << 16)
+    plans = {n: bz.make_plan_desc(n=n, L=L, m=M, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP32)
+             for n in sizes}
+
+    def wait(t):
+        while True:
+            done, r = srv.poll(t)
+            if done:
+                return r
+            time.sleep(0.0002)
+    for n in sizes:  # build and upload every plan before timing
+        q = torch.empty((16, n, n, n), dtype=torch.float64, device="cuda")
+        wait(srv.submit(pool[n][:16], q, plans[n]))
+    lat, cells, failed = [], [0], [0]
+    lock = threading.Lock()
+    stop_at = time.perf_counter() + seconds
+
+    def client(cid):
+        rng = np.random.default_rng(seed * 100 + cid)
+        bufs = {n: [torch.empty((4096, n, n, n), dtype=torch.float64, device="cuda") for _ in range(2)]
+                for n in sizes}
+        out = []
+        slot = 0
+        while time.perf_counter() < stop_at:
+            n = int(rng.choice(sizes))
+            k = int(np.clip(rng.poisson(512), 16, 4096))
+            if len(out) == 2:
+                r, kk = wait(out.pop(0))
+                with lock:
+                    if r.state == bz.BZ_REQ_DONE:
+                        lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+                        cells[0] += kk
+                    else:
+                        failed[0] += 1
+            t = srv.submit(pool[n][:k], bufs[n][slot][:k], plans[n], client_id=cid)
+            slot ^= 1
+            out.append((t, k))
+        for t, kk in out:
+            r = wait(t)
+            with lock:
+                lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+                cells[0] += kk
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    dt = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    return {"clients": 4, "sizes": list(sizes), "m": M, "requests": int(lat.size), "failed": failed[0],
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "cells_per_s": cells[0] / dt, "seconds": dt, "arena_peak_gib": st.arena_peak / 2 ** 30,
+            "workload": "4 clients x 2 in flight, N in {16,24,32,48}, M=32, Poisson(512) cells in [16,4096], "
+                        "FP32 + FP64 projection, 16 GiB arena"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +149,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run length (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -122,7 +200,9 @@ def main():
     v64 = CELLS * k64 / (time.perf_counter() - t0)
     q32 = out.cpu().numpy()
     q64 = out64.cpu().numpy()
-    diff = np.linalg.norm((q32 - q64).reshape(CELLS, -1), axis=1) / np.linalg.norm(q64.reshape(CELLS, -1), axis=1)
+    dq = (q32 - q64).reshape(CELLS, -1)
+    diff = np.linalg.norm(dq, axis=1) / np.linalg.norm(q64.reshape(CELLS, -1), axis=1)
+    batch_rel = float(np.linalg.norm(dq) / np.linalg.norm(q64))
 
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -159,9 +239,15 @@ def main():
                       "total": stage_ms[3]},
         "fp64_plain_value": v64,
         "speedup_vs_fp64_plain": value / v64,
-        "fp32_vs_fp64_rel_l2": {"max": float(diff.max()), "median": float(np.median(diff))},
+        "fp32_vs_fp64_rel_l2": {"batch": batch_rel, "median_cell": float(np.median(diff)),
+                                "max_cell_unfloored": float(diff.max())},
         "algorithmic_tflops_whole_step": total_flops * value / 1e12,
     }
+    if args.serve_seconds > 0:
+        del out64, col64
+        torch.cuda.empty_cache()
+        rec["serving"] = serving_run(args.serve_seconds)
+        rec["p99_latency_ms"] = rec["serving"]["p99_ms"]
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(f_np, args.cpu_budget)
     print(json.dumps(rec))

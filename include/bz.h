@@ -225,6 +225,103 @@ bz_status bz_realizability_mask(const bz_mask_desc* desc, const double* rho, con
                                 const uint8_t* cell_flags, uint8_t* regime_out,
                                 int32_t* boltz_idx, int32_t* counts, double* diag, void* stream);
 
+/*
+ * Serving: continuous batching of collision evaluations from several
+ * concurrent simulations on one GPU (each dynamic re-partition of a
+ * simulation produces a request with its own grid size and cell count).
+ *
+ * The server carves plan tables and per-request workspaces out of one
+ * caller-owned device arena; it never allocates device memory.  Requests are
+ * admitted in arrival order as soon as their workspace fits in the arena and
+ * an in-flight slot is free (a request that does not fit may be passed by at
+ * most 8 later ones); admitted requests run on n_streams streams, so their
+ * work overlaps on the device.  Plans are cached by descriptor (max_cells is
+ * ignored) and evicted least-recently-used when idle and memory is short.
+ * Request buffers (f, idx, q) must stay valid and unmodified until
+ * bz_serve_poll reports DONE or FAILED.  A request's result does not depend
+ * on the other requests in flight.  A request whose descriptor is invalid
+ * or whose workspace can never fit in the arena ends FAILED (err set) without
+ * affecting the others.
+ */
+typedef struct bz_server bz_server;
+
+typedef struct {
+  void* arena_dev;      /* device arena, 256-byte aligned, owned by the caller */
+  size_t arena_bytes;
+  int32_t max_inflight; /* requests on the GPU at once (>= 1) */
+  int32_t n_streams;    /* launch streams (1..16), default priority */
+  int32_t max_queue;    /* queued requests before bz_serve_submit returns BZ_AGAIN */
+} bz_server_desc;
+
+typedef struct {
+  bz_plan_desc plan;    /* operator (dirs/weights copied at submission for explicit rules) */
+  const void* f;        /* device [*][n][n][n], f_dtype */
+  int32_t f_dtype;      /* BZ_FP64 | BZ_FP32 */
+  const int32_t* idx;   /* device [ncells] or NULL (rows 0..ncells) */
+  int32_t ncells;
+  void* q;              /* device output as for bz_collide_batch */
+  int32_t flags;        /* BZ_SCATTER */
+  int32_t client_id;    /* caller's tag, unused by the server */
+} bz_request;
+
+enum { BZ_REQ_QUEUED = 0, BZ_REQ_ADMITTED = 1, BZ_REQ_DONE = 2, BZ_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;        /* BZ_REQ_* */
+  bz_status err;        /* BZ_OK, or the error of a FAILED request */
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady-clock timestamps */
+} bz_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed;
+  int32_t queued, inflight, plans_cached;
+  size_t arena_used, arena_peak;  /* bytes (tables + workspaces) */
+  double p50_ms, p99_ms;          /* submit-to-done latency of completed requests */
+  double cells_per_s;             /* completed cells / (last done - first submit) */
+} bz_server_stats_t;
+
+/* Start a server (one scheduler thread) on the current device. */
+bz_status bz_server_create(const bz_server_desc* desc, bz_server** out);
+/* Queue a request; *ticket identifies it.  BZ_AGAIN if the queue is full. */
+bz_status bz_serve_submit(bz_server* server, const bz_request* req, uint64_t* ticket);
+/* BZ_OK with *out filled once the request is DONE or FAILED (the ticket is then
+   released), BZ_AGAIN (with the current state) while it is queued or running,
+   BZ_ERR_ARG for an unknown ticket. */
+bz_status bz_serve_poll(bz_server* server, uint64_t ticket, bz_result* out);
+bz_status bz_server_stats(bz_server* server, bz_server_stats_t* out);
+/* Run every queued and in-flight request to completion, then free the server. */
+bz_status bz_server_destroy(bz_server* server);
+
+/*
+ * One time step of the hot path captured as a HIP graph (built once, replayed
+ * every step): bz_realizability_mask on the macro fields, then
+ * bz_collide_batch over the regime-2 cells it lists (count read on the GPU,
+ * output scattered to rows boltz_idx of q, FP64 projected), then regime_out
+ * copied over regime_in so that the next replay continues from the new
+ * regimes.  The caller refreshes the contents of the buffers between replays;
+ * the pointers are fixed at creation.  The plan must be bound with capacity
+ * >= nx*ny and project = 1.  Replays on one plan must be ordered on one stream.
+ */
+typedef struct bz_step bz_step;
+typedef struct {
+  const double *rho, *ux, *uy, *T, *eps; /* [ny][nx] macro fields */
+  uint8_t* regime_in;                    /* [ny][nx], overwritten by each replay */
+  const double* l1dist;                  /* or NULL */
+  const uint8_t* cell_flags;             /* or NULL */
+  uint8_t* regime_out;                   /* [ny][nx] */
+  int32_t* boltz_idx;                    /* [nx*ny] */
+  int32_t* counts;                       /* [2] as for bz_realizability_mask */
+  double* diag;                          /* or NULL */
+  const void* f;                         /* [nx*ny][n][n][n], f_dtype */
+  int32_t f_dtype;
+  double* q;                             /* [nx*ny][n][n][n] FP64; only rows listed are written */
+} bz_step_buffers;
+
+bz_status bz_step_create(const bz_plan* plan, const bz_mask_desc* mask, const bz_step_buffers* bufs,
+                         bz_step** out);
+bz_status bz_step_launch(bz_step* step, void* stream);
+bz_status bz_step_destroy(bz_step* step);
+
 #ifdef __cplusplus
 }
 #endif

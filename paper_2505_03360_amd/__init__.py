@@ -59,6 +59,40 @@ class BzMaskDesc(ctypes.Structure):
     ]
 
 
+class BzServerDesc(ctypes.Structure):
+    _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("max_inflight", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+
+
+class BzRequest(ctypes.Structure):
+    _fields_ = [("plan", BzPlanDesc), ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32),
+                ("idx", ctypes.c_void_p), ("ncells", ctypes.c_int32), ("q", ctypes.c_void_p),
+                ("flags", ctypes.c_int32), ("client_id", ctypes.c_int32)]
+
+
+class BzResult(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("err", ctypes.c_int32), ("t_submit_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class BzServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("queued", ctypes.c_int32), ("inflight", ctypes.c_int32), ("plans_cached", ctypes.c_int32),
+                ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("cells_per_s", ctypes.c_double)]
+
+
+BZ_REQ_QUEUED, BZ_REQ_ADMITTED, BZ_REQ_DONE, BZ_REQ_FAILED = 0, 1, 2, 3
+
+
+class BzStepBuffers(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p),
+                ("T", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("regime_in", ctypes.c_void_p),
+                ("l1dist", ctypes.c_void_p), ("cell_flags", ctypes.c_void_p), ("regime_out", ctypes.c_void_p),
+                ("boltz_idx", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("diag", ctypes.c_void_p),
+                ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32), ("q", ctypes.c_void_p)]
+
+
 class BzError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"bz error {code}: {msg}")
@@ -87,6 +121,14 @@ SIGNATURES = [
     ("bz_plan_last_times", _I32, [_VP, ctypes.POINTER(ctypes.c_float), _I32]),
     ("bz_realizability_mask", _I32, [ctypes.POINTER(BzMaskDesc), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("bz_server_create", _I32, [ctypes.POINTER(BzServerDesc), ctypes.POINTER(_VP)]),
+    ("bz_serve_submit", _I32, [_VP, ctypes.POINTER(BzRequest), ctypes.POINTER(ctypes.c_uint64)]),
+    ("bz_serve_poll", _I32, [_VP, ctypes.c_uint64, ctypes.POINTER(BzResult)]),
+    ("bz_server_stats", _I32, [_VP, ctypes.POINTER(BzServerStats)]),
+    ("bz_server_destroy", _I32, [_VP]),
+    ("bz_step_create", _I32, [_VP, ctypes.POINTER(BzMaskDesc), ctypes.POINTER(BzStepBuffers), ctypes.POINTER(_VP)]),
+    ("bz_step_launch", _I32, [_VP, _VP]),
+    ("bz_step_destroy", _I32, [_VP]),
 ]
 
 
@@ -212,6 +254,50 @@ def bz_realizability_mask(desc: BzMaskDesc, rho: int, ux: int, uy: int, T: int, 
                                        cell_flags, regime_out, boltz_idx, counts, diag, stream))
 
 
+def bz_server_create(desc: BzServerDesc) -> int:
+    out = _VP()
+    _check(lib().bz_server_create(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def bz_serve_submit(server: int, req: BzRequest):
+    """Returns the ticket, or None if the queue is full (BZ_AGAIN)."""
+    t = ctypes.c_uint64()
+    rc = _check(lib().bz_serve_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return None if rc == BZ_AGAIN else t.value
+
+
+def bz_serve_poll(server: int, ticket: int):
+    """Returns (finished, BzResult)."""
+    r = BzResult()
+    rc = _check(lib().bz_serve_poll(server, ticket, ctypes.byref(r)))
+    return rc == BZ_OK, r
+
+
+def bz_server_stats(server: int) -> BzServerStats:
+    st = BzServerStats()
+    _check(lib().bz_server_stats(server, ctypes.byref(st)))
+    return st
+
+
+def bz_server_destroy(server: int) -> None:
+    _check(lib().bz_server_destroy(server))
+
+
+def bz_step_create(plan: int, mask: BzMaskDesc, bufs: BzStepBuffers) -> int:
+    out = _VP()
+    _check(lib().bz_step_create(plan, ctypes.byref(mask), ctypes.byref(bufs), ctypes.byref(out)))
+    return out.value
+
+
+def bz_step_launch(step: int, stream: int = 0) -> None:
+    _check(lib().bz_step_launch(step, stream))
+
+
+def bz_step_destroy(step: int) -> None:
+    _check(lib().bz_step_destroy(step))
+
+
 # ---------------------------------------------------------------- torch-side helpers
 def _torch():
     import torch
@@ -265,6 +351,59 @@ class Collider:
         if self.plan:
             bz_plan_destroy(self.plan)
             self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving runtime whose arena is one torch uint8 tensor."""
+
+    def __init__(self, arena_bytes: int, max_inflight: int = 8, n_streams: int = 4, max_queue: int = 4096,
+                 device="cuda"):
+        torch = _torch()
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
+        d = BzServerDesc()
+        d.arena_dev, d.arena_bytes = _ptr(self.arena), arena_bytes
+        d.max_inflight, d.n_streams, d.max_queue = max_inflight, n_streams, max_queue
+        torch.cuda.synchronize()
+        self.handle = bz_server_create(d)
+        self._keep = {}
+
+    def submit(self, f, q, plan: BzPlanDesc, idx=None, ncells=None, scatter=False, client_id=0):
+        torch = _torch()
+        n3 = plan.n ** 3
+        r = BzRequest()
+        r.plan = plan
+        r.f = _ptr(f)
+        r.f_dtype = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
+        r.idx = _ptr(idx)
+        r.ncells = ncells if ncells is not None else (idx.numel() if idx is not None else f.numel() // n3)
+        r.q = _ptr(q)
+        r.flags = BZ_SCATTER if scatter else 0
+        r.client_id = client_id
+        t = bz_serve_submit(self.handle, r)
+        if t is not None:
+            self._keep[t] = (f, q, idx, plan)
+        return t
+
+    def poll(self, ticket):
+        done, res = bz_serve_poll(self.handle, ticket)
+        if done:
+            self._keep.pop(ticket, None)
+        return done, res
+
+    def stats(self) -> BzServerStats:
+        return bz_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            bz_server_destroy(self.handle)
+            self.handle = 0
+            self._keep.clear()
 
     def __del__(self):
         try:

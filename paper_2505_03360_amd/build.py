@@ -23,6 +23,7 @@ SOURCES = [
     ("mask.hip", ["-ffp-contract=off"]),
     ("plan.cpp", []),
     ("server.cpp", []),
+    ("step.cpp", []),
 ]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

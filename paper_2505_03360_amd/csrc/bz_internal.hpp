@@ -24,6 +24,15 @@ struct WsLayout {
   size_t fh_cell, y_cell, acc_cell;  // bytes per cell of each region
 };
 
+// Device memory one evaluation runs on: the plan's uploaded tables and a
+// workspace holding `capacity` cells.
+struct Binding {
+  const void* tables = nullptr;
+  void* ws = nullptr;
+  int capacity = 0;
+  WsLayout lay{};
+};
+
 }  // namespace bz
 
 struct bz_plan {
@@ -51,7 +60,7 @@ struct bz_plan {
   void* ws_dev = nullptr;
   size_t ws_bytes = 0;
   int capacity = 0;
-  bz::WsLayout ws{};
+  bz::WsLayout ws{};  // per-cell region sizes; offsets of the plan's own binding
   // timing: a ring of event quadruples, one per timed call
   static constexpr int kTimingSlots = 512;
   bool timing = false;
@@ -62,10 +71,13 @@ struct bz_plan {
 };
 
 namespace bz {
-// kernel launchers (collide.hip)
-bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int32_t* idx,
-                         int ncells, const int32_t* ncells_dev, void* q, int scatter,
-                         hipStream_t s);
+// kernel launchers (collide.hip); `timed` records the plan's timing events
+bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
+                         const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
+                         int scatter, hipStream_t s, bool timed);
+// plan helpers (plan.cpp)
+Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
+bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
 bool fused_supported(int n, int fp32);
 int fused_default_chunks(int n);
 }  // namespace bz

@@ -206,6 +206,23 @@ __global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ fused FP32
+// Global-address-space pointer whose value the compiler cannot see through:
+// per-pass load bases stay in the pass loop (the compiler would otherwise
+// hoist every base + k*stride address out of it, 2 registers each), and the
+// loads remain global (not flat) loads with immediate offsets.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = const T*;
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> opaque_global(const T* p) {
+  asm volatile("" : "+v"(p));
+  return (gptr<T>)p;
+}
+
 struct FusedArgs {
   int ncells;
   const int32_t* ncells_dev;
@@ -219,6 +236,12 @@ struct FusedArgs {
   const cx<float>* mult;
   const float* w;
   int m1, chunks;
+  // epilogue with the conservative projection (single-chunk plans)
+  int fuse_project;
+  int scatter;
+  double C, dv;
+  double ginv[25];
+  double* q;
 };
 
 // N^2/S threads; S j3-slices of width W = N/S.
@@ -244,6 +267,75 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   // other slices stay in registers until their turn.
   cx<float> rest[S > 1 ? S : 1][S > 1 ? N - W : 1];
   __syncthreads();  // LDS free: the previous pass's stage C has read it
+  if constexpr (S == 2) {
+    // Mirror pairing: thread (k1, k2), k2 < N/2, loads pencil (k1, k2, :) and
+    // also forms its mirror (-k1, -k2, :): the multipliers are even and fhat
+    // of a real f is Hermitian, so X(-k1,-k2,k3) = M(k1,k2,-k3) conj(F(k1,k2,-k3)).
+    // Row k2 = 0 is its own mirror row; its threads take row N/2 instead,
+    // which is zero in the gain passes (the multipliers vanish on the Nyquist
+    // planes) and loaded directly in the loss pass.
+    const int k1 = t % N, k2 = t / N;
+    const bool row0 = k2 == 0;
+    const int k1b = row0 ? k1 : (N - k1) % N;
+    const int k2b = row0 ? N / 2 : N - k2;
+    const size_t off = size_t(k2) * N * N + k1;
+    const gptr<cx<float>> fb = opaque_global(fhc + off);
+    const gptr<cx<float>> mb = opaque_global(mp + off);
+    {
+      // pencil (k1, k2): X = M F
+      cx<float> xa[N];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+          const cx<float> F = fb[k3 * N], Mu = mb[k3 * N];
+          xa[k3] = {Mu.x * F.x - Mu.y * F.y, Mu.x * F.y + Mu.y * F.x};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      bzk::fft<N, 1>(xa);
+#pragma unroll
+      for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = xa[j];
+#pragma unroll
+      for (int j = W; j < N; ++j) rest[0][j - W] = xa[j];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      // mirror pencil (-k1, -k2): X(k3) = M(-k3) conj(F(-k3)), the same lines
+      // re-read (cache hits) so that only one pencil is live at a time
+      cx<float> xb[N];
+      if (row0) {
+        if constexpr (LOSS) {
+          const gptr<cx<float>> fr = opaque_global(fhc + size_t(N / 2) * N * N + k1);
+          const gptr<cx<float>> mr = opaque_global(mp + size_t(N / 2) * N * N + k1);
+#pragma unroll
+          for (int k3 = 0; k3 < N; ++k3) {
+            const cx<float> F = fr[k3 * N], Mu = mr[k3 * N];
+            xb[k3] = {Mu.x * F.x - Mu.y * F.y, Mu.x * F.y + Mu.y * F.x};
+          }
+        } else {
+#pragma unroll
+          for (int k3 = 0; k3 < N; ++k3) xb[k3] = {0.0f, 0.0f};
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+            const int m3 = (N - k3) % N;
+            const cx<float> F = fb[m3 * N], Mu = mb[m3 * N];
+            xb[k3] = {Mu.x * F.x + Mu.y * F.y, Mu.y * F.x - Mu.x * F.y};  // (a + ib) conj(F)
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      bzk::fft<N, 1>(xb);
+#pragma unroll
+      for (int j = 0; j < W; ++j) lds[(k2b * N + k1b) * AB + j] = xb[j];
+#pragma unroll
+      for (int j = W; j < N; ++j) rest[1][j - W] = xb[j];
+    }
+  } else {
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     const int P = q * T + t;
@@ -252,9 +344,8 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     // Opaque per-pass bases: keeps the compiler from hoisting the n
     // per-element addresses out of the pass loop (they would occupy 2n
     // registers); loads then use base + immediate offsets.
-    const cx<float>* fb = fhc + off;
-    const cx<float>* mb = mp + off;
-    asm volatile("" : "+v"(fb), "+v"(mb));
+    const gptr<cx<float>> fb = opaque_global(fhc + off);
+    const gptr<cx<float>> mb = opaque_global(mp + off);
     cx<float> x[N];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -274,14 +365,23 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       for (int j = W; j < N; ++j) rest[q][j - W] = x[j];
     }
   }
+  }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     if (s > 0) {
       __syncthreads();  // stage C of the previous slice has read the LDS
 #pragma unroll
       for (int q = 0; q < S; ++q) {
-        const int P = q * T + t;
-        const int k1 = P % N, k2 = P / N;
+        int k1, k2;
+        if constexpr (S == 2) {
+          const int ka = t % N, kb = t / N;
+          k1 = q == 0 ? ka : (kb == 0 ? ka : (N - ka) % N);
+          k2 = q == 0 ? kb : (kb == 0 ? N / 2 : N - kb);
+        } else {
+          const int P = q * T + t;
+          k1 = P % N;
+          k2 = P / N;
+        }
 #pragma unroll
         for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = rest[q][(s - 1) * W + j];
       }
@@ -348,8 +448,70 @@ __global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
   const int gain_end = p1 < a.m1 - 1 ? p1 : a.m1 - 1;
   for (int p = p0; p < gain_end; ++p) fused_pass<N, S, false>(a, lds, fhc, row, p, t, acc);
   if (p1 == a.m1) fused_pass<N, S, true>(a, lds, fhc, row, a.m1 - 1, t, acc);
-  float* out = a.acc + cell * a.acc_stride + size_t(chunk) * N * N * N;
   const int j2 = t / W, tl = t % W;
+  if (a.fuse_project) {
+    // Q = C acc; moments m = sum_j (1, v1, v2, v3, |v|^2) Q_j in FP64 with a
+    // fixed reduction order (per thread, then across the wave, then across
+    // the waves); lambda = (C C^T)^-1 m; q = Q - (l0 + l1 v1 + ... + l4 |v|^2).
+    const double v2 = (j2 - N / 2) * a.dv;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double v3 = (s * W + tl - N / 2) * a.dv;
+#pragma unroll
+      for (int j1 = 0; j1 < N; ++j1) {
+        const double v1 = (j1 - N / 2) * a.dv;
+        const double qv = a.C * double(acc[s][j1]);
+        m[0] += qv;
+        m[1] += v1 * qv;
+        m[2] += v2 * qv;
+        m[3] += v3 * qv;
+        m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m[k] += __shfl_xor(m[k], o);
+    constexpr int NW = (N * N / S) / 64;
+    double* red = reinterpret_cast<double*>(lds);
+    __syncthreads();  // the last pass's stage C has read the LDS
+    if ((t & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) red[k * NW + t / 64] = m[k];
+    __syncthreads();
+    double lam[5];
+    {
+      double tot[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        double x = 0.0;
+        for (int wv = 0; wv < NW; ++wv) x += red[k * NW + wv];
+        tot[k] = x;
+      }
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x += a.ginv[5 * i + k] * tot[k];
+        lam[i] = x;
+      }
+    }
+    const long orow = a.scatter ? row : long(cell);
+    double* q = a.q + size_t(orow) * N * N * N;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double v3 = (s * W + tl - N / 2) * a.dv;
+#pragma unroll
+      for (int j1 = 0; j1 < N; ++j1) {
+        const double v1 = (j1 - N / 2) * a.dv;
+        const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
+        q[size_t(j1) * N * N + size_t(j2) * N + s * W + tl] = a.C * double(acc[s][j1]) - corr;
+      }
+    }
+    return;
+  }
+  float* out = a.acc + cell * a.acc_stride + size_t(chunk) * N * N * N;
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -465,26 +627,27 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
 }
 
 template <typename T>
-bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStream_t s, bool fwd_only) {
+bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStream_t s, bool fwd_only,
+                    bool timed) {
   switch (p->n) {
     case 16:
       launch_plain_forward<T, 16>(a, ncells, s);
-      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (timed) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
       if (!fwd_only) launch_plain_dirs<T, 16>(a, ncells, p->m1, s);
       break;
     case 24:
       launch_plain_forward<T, 24>(a, ncells, s);
-      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (timed) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
       if (!fwd_only) launch_plain_dirs<T, 24>(a, ncells, p->m1, s);
       break;
     case 32:
       launch_plain_forward<T, 32>(a, ncells, s);
-      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (timed) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
       if (!fwd_only) launch_plain_dirs<T, 32>(a, ncells, p->m1, s);
       break;
     case 48:
       launch_plain_forward<T, 48>(a, ncells, s);
-      if (p->timing) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
+      if (timed) (void)hipEventRecord(const_cast<bz_plan*>(p)->ev[1], s);
       if (!fwd_only) launch_plain_dirs<T, 48>(a, ncells, p->m1, s);
       break;
     default:
@@ -507,13 +670,14 @@ bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
 
 int fused_default_chunks(int n) { return 1; }
 
-bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int32_t* idx,
-                         int ncells, const int32_t* ncells_dev, void* q, int scatter,
-                         hipStream_t s) {
+bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
+                         const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
+                         int scatter, hipStream_t s, bool timed) {
   bz_plan* pm = const_cast<bz_plan*>(p);
-  char* ws = static_cast<char*>(p->ws_dev);
+  char* ws = static_cast<char*>(b.ws);
+  const WsLayout& lay = b.lay;
   const size_t n3 = size_t(p->n) * p->n * p->n;
-  if (p->timing) {
+  if (timed) {
     pm->ev = &pm->evs[4 * (pm->timed_calls % bz_plan::kTimingSlots)];
     (void)hipEventRecord(pm->ev[0], s);
   }
@@ -523,10 +687,10 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
   pa.ncells_dev = ncells_dev;
   pa.idx = idx;
   pa.scatter = scatter;
-  pa.acc = ws + p->ws.acc_off;
+  pa.acc = ws + lay.acc_off;
   pa.acc_fp32 = p->fp32;
   pa.chunks = p->transform == BZ_XF_FUSED ? p->chunks : 1;
-  pa.acc_stride = p->ws.acc_cell / (p->fp32 ? 4 : 8);
+  pa.acc_stride = lay.acc_cell / (p->fp32 ? 4 : 8);
   pa.C = p->C;
   pa.dv = p->dv;
   for (int i = 0; i < 25; ++i) pa.ginv[i] = p->ginv[i];
@@ -534,6 +698,7 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
   pa.q = q;
   pa.q_fp32 = p->fp32;
   bz_status st = BZ_OK;
+  bool fused_projection = false;
   if (p->fp32) {
     PlainArgs<float> a{};
     a.f = f;
@@ -541,16 +706,16 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
     a.idx = idx;
     a.ncells = ncells;
     a.ncells_dev = ncells_dev;
-    a.fh = reinterpret_cast<cx<float>*>(ws + p->ws.fh_off);
-    a.y = reinterpret_cast<cx<float>*>(ws + p->ws.y_off);
-    a.acc = reinterpret_cast<float*>(ws + p->ws.acc_off);
-    a.fh_stride = p->ws.fh_cell / sizeof(cx<float>);
-    a.y_stride = p->ws.y_cell / sizeof(cx<float>);
-    a.acc_stride = p->ws.acc_cell / sizeof(float);
-    a.mult = static_cast<const cx<float>*>(p->tables_dev);
-    a.w = reinterpret_cast<const float*>(static_cast<const char*>(p->tables_dev) + p->table_w_off);
+    a.fh = reinterpret_cast<cx<float>*>(ws + lay.fh_off);
+    a.y = reinterpret_cast<cx<float>*>(ws + lay.y_off);
+    a.acc = reinterpret_cast<float*>(ws + lay.acc_off);
+    a.fh_stride = lay.fh_cell / sizeof(cx<float>);
+    a.y_stride = lay.y_cell / sizeof(cx<float>);
+    a.acc_stride = lay.acc_cell / sizeof(float);
+    a.mult = static_cast<const cx<float>*>(b.tables);
+    a.w = reinterpret_cast<const float*>(static_cast<const char*>(b.tables) + p->table_w_off);
     if (p->transform == BZ_XF_FUSED) {
-      st = run_plain<float>(p, a, ncells, s, true);
+      st = run_plain<float>(p, a, ncells, s, true, timed);
       if (st != BZ_OK) return st;
       FusedArgs fa{};
       fa.ncells = ncells;
@@ -566,11 +731,18 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
       fa.w = a.w;
       fa.m1 = p->m1;
       fa.chunks = p->chunks;
+      fa.fuse_project = (p->chunks == 1 && p->project) ? 1 : 0;
+      fa.scatter = scatter;
+      fa.C = p->C;
+      fa.dv = p->dv;
+      for (int i = 0; i < 25; ++i) fa.ginv[i] = p->ginv[i];
+      fa.q = static_cast<double*>(q);
+      fused_projection = fa.fuse_project != 0;
       if (p->n == 32) launch_fused<32, 2>(fa, ncells, s);
       else if (p->n == 16) launch_fused<16, 1>(fa, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
     } else {
-      st = run_plain<float>(p, a, ncells, s, false);
+      st = run_plain<float>(p, a, ncells, s, false, timed);
     }
   } else {
     PlainArgs<double> a{};
@@ -579,20 +751,20 @@ bz_status launch_collide(const bz_plan* p, const void* f, int f_fp32, const int3
     a.idx = idx;
     a.ncells = ncells;
     a.ncells_dev = ncells_dev;
-    a.fh = reinterpret_cast<cx<double>*>(ws + p->ws.fh_off);
-    a.y = reinterpret_cast<cx<double>*>(ws + p->ws.y_off);
-    a.acc = reinterpret_cast<double*>(ws + p->ws.acc_off);
-    a.fh_stride = p->ws.fh_cell / sizeof(cx<double>);
-    a.y_stride = p->ws.y_cell / sizeof(cx<double>);
-    a.acc_stride = p->ws.acc_cell / sizeof(double);
-    a.mult = static_cast<const cx<double>*>(p->tables_dev);
-    a.w = reinterpret_cast<const double*>(static_cast<const char*>(p->tables_dev) + p->table_w_off);
-    st = run_plain<double>(p, a, ncells, s, false);
+    a.fh = reinterpret_cast<cx<double>*>(ws + lay.fh_off);
+    a.y = reinterpret_cast<cx<double>*>(ws + lay.y_off);
+    a.acc = reinterpret_cast<double*>(ws + lay.acc_off);
+    a.fh_stride = lay.fh_cell / sizeof(cx<double>);
+    a.y_stride = lay.y_cell / sizeof(cx<double>);
+    a.acc_stride = lay.acc_cell / sizeof(double);
+    a.mult = static_cast<const cx<double>*>(b.tables);
+    a.w = reinterpret_cast<const double*>(static_cast<const char*>(b.tables) + p->table_w_off);
+    st = run_plain<double>(p, a, ncells, s, false, timed);
   }
   if (st != BZ_OK) return st;
-  if (p->timing) (void)hipEventRecord(pm->ev[2], s);
-  hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
-  if (p->timing) {
+  if (timed) (void)hipEventRecord(pm->ev[2], s);
+  if (!fused_projection) hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  if (timed) {
     (void)hipEventRecord(pm->ev[3], s);
     pm->timed_calls += 1;
   }

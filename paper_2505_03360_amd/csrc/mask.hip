@@ -145,7 +145,18 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t* reg, int ncell,
   if (t == 0) counts[0] = base_s;
 }
 
+__global__ void k_copy_u8(const uint8_t* src, uint8_t* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 }  // namespace
+
+namespace bz {
+void launch_copy_u8(const uint8_t* src, uint8_t* dst, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_u8, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+}
+}  // namespace bz
 
 extern "C" bz_status bz_realizability_mask(const bz_mask_desc* d, const double* rho, const double* ux,
                                            const double* uy, const double* T, const double* eps,

@@ -276,6 +276,48 @@ void layout(bz_plan* p) {
   p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell;
 }
 
+
+}  // namespace
+
+Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes) {
+  Binding b;
+  b.tables = tables;
+  b.ws = ws;
+  const size_t cap = ws_bytes >= p->ws_fixed + p->ws_per_cell ? (ws_bytes - p->ws_fixed) / p->ws_per_cell : 0;
+  b.capacity = int(std::min<size_t>(cap, size_t(1) << 30));
+  b.lay = p->ws;
+  b.lay.fh_off = p->ws_fixed;
+  b.lay.y_off = b.lay.fh_off + size_t(b.capacity) * b.lay.fh_cell;
+  b.lay.acc_off = b.lay.y_off + size_t(b.capacity) * b.lay.y_cell;
+  return b;
+}
+
+bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
+  const size_t n3 = size_t(p->n) * p->n * p->n;
+  std::vector<unsigned char> host(p->tables_bytes, 0);
+  const size_t entries = size_t(p->m1) * n3;
+  if (p->fp32) {
+    float* m = reinterpret_cast<float*>(host.data());
+    for (size_t e = 0; e < entries; ++e) {
+      double re, im;
+      device_multiplier(p, int(e / n3), e % n3, re, im);
+      m[2 * e] = float(re);
+      m[2 * e + 1] = float(im);
+    }
+    float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
+    for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
+  } else {
+    double* m = reinterpret_cast<double*>(host.data());
+    for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
+    std::memcpy(host.data() + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
+  }
+  hipError_t e = hipMemcpyAsync(tables_dev, host.data(), p->tables_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(BZ_ERR_DEVICE, "table upload failed: %s", hipGetErrorString(e));
+  return BZ_OK;
+}
+
+namespace {
 }  // namespace
 }  // namespace bz
 
@@ -384,33 +426,11 @@ bz_status bz_plan_bind(bz_plan* p, void* tables_dev, void* ws_dev, size_t ws_byt
     return fail(BZ_ERR_ARG, "bz_plan_bind: buffers must be 256-byte aligned");
   if (ws_bytes < p->ws_fixed + p->ws_per_cell)
     return fail(BZ_ERR_NOMEM, "bz_plan_bind: workspace %zu bytes < one cell (%zu)", ws_bytes, p->ws_fixed + p->ws_per_cell);
-  const size_t cap = (ws_bytes - p->ws_fixed) / p->ws_per_cell;
-  p->capacity = int(std::min<size_t>(cap, size_t(1) << 30));
-  p->ws.fh_off = p->ws_fixed;
-  p->ws.y_off = p->ws.fh_off + size_t(p->capacity) * p->ws.fh_cell;
-  p->ws.acc_off = p->ws.y_off + size_t(p->capacity) * p->ws.y_cell;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t n3 = size_t(p->n) * p->n * p->n;
-  std::vector<unsigned char> host(p->tables_bytes, 0);
-  const size_t entries = size_t(p->m1) * n3;
-  if (p->fp32) {
-    float* m = reinterpret_cast<float*>(host.data());
-    for (size_t e = 0; e < entries; ++e) {
-      double re, im;
-      device_multiplier(p, int(e / n3), e % n3, re, im);
-      m[2 * e] = float(re);
-      m[2 * e + 1] = float(im);
-    }
-    float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
-    for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
-  } else {
-    double* m = reinterpret_cast<double*>(host.data());
-    for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
-    std::memcpy(host.data() + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
-  }
-  hipError_t e = hipMemcpyAsync(tables_dev, host.data(), p->tables_bytes, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return fail(BZ_ERR_DEVICE, "bz_plan_bind: table upload failed: %s", hipGetErrorString(e));
+  const bz_status st = upload_tables(p, tables_dev, static_cast<hipStream_t>(stream));
+  if (st != BZ_OK) return st;
+  const Binding b = make_binding(p, tables_dev, ws_dev, ws_bytes);
+  p->capacity = b.capacity;
+  p->ws = b.lay;
   p->tables_dev = tables_dev;
   p->ws_dev = ws_dev;
   p->ws_bytes = ws_bytes;
@@ -510,8 +530,13 @@ bz_status bz_collide_batch(const bz_plan* p, const void* f, int32_t f_dtype, con
   if ((flags & BZ_SCATTER) && !idx) return fail(BZ_ERR_ARG, "bz_collide_batch: BZ_SCATTER needs idx");
   if (ncells > p->capacity)
     return fail(BZ_ERR_NOMEM, "bz_collide_batch: %d cells exceed the bound capacity %d", ncells, p->capacity);
-  return launch_collide(p, f, f_dtype == BZ_FP32, idx, ncells, ncells_dev, q,
-                        (flags & BZ_SCATTER) != 0, static_cast<hipStream_t>(stream));
+  Binding b;
+  b.tables = p->tables_dev;
+  b.ws = p->ws_dev;
+  b.capacity = p->capacity;
+  b.lay = p->ws;
+  return launch_collide(p, b, f, f_dtype == BZ_FP32, idx, ncells, ncells_dev, q,
+                        (flags & BZ_SCATTER) != 0, static_cast<hipStream_t>(stream), p->timing);
 }
 
 }  // extern "C"

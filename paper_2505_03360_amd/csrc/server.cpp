@@ -1,1 +1,471 @@
-// placeholder; serving runtime follows
+// Serving runtime: continuous batching of collision-evaluation requests from
+// several concurrent simulations on one GPU.
+//
+// Requests arrive from any client thread (bz_serve_submit) with their own
+// operator descriptor, distribution buffer, cell list and output buffer.  One
+// scheduler thread
+//   * admits queued requests in arrival order as soon as their workspace
+//     (ws_per_cell * cells bytes) fits in the caller's arena and an in-flight
+//     slot is free; a request that does not fit may be passed by later ones
+//     at most kMaxBypass times, after which admission waits for it;
+//   * keeps one plan per operator descriptor (tables uploaded once into the
+//     arena, evicted least-recently-used when idle and memory is short);
+//   * launches each admitted request on one of n_streams streams, so the
+//     work of concurrent requests overlaps on the device, and records an
+//     event after it;
+//   * polls those events, frees the workspace and timestamps completion.
+// A request's arithmetic does not depend on the other requests (each has its
+// own workspace; per-cell arithmetic is independent of the batch), so its
+// result is the same alone and in the mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "bz_internal.hpp"
+
+namespace {
+
+constexpr int kMaxBypass = 8;
+constexpr size_t kAlign = 256;
+
+uint64_t now_ns() {
+  return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                      std::chrono::steady_clock::now().time_since_epoch())
+                      .count());
+}
+
+// First-fit allocator over the caller's arena, 256-byte granules.
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0, used = 0, peak = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+  void init(void* b, size_t n) {
+    base = static_cast<char*>(b);
+    bytes = n & ~(kAlign - 1);
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  bool alloc(size_t sz, size_t* off) {
+    sz = bz::align256(std::max<size_t>(sz, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= sz) {
+        *off = it->first;
+        const size_t rest = it->second - sz;
+        const size_t roff = it->first + sz;
+        free_.erase(it);
+        if (rest) free_[roff] = rest;
+        used += sz;
+        peak = std::max(peak, used);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t sz) {
+    sz = bz::align256(std::max<size_t>(sz, 1));
+    used -= sz;
+    auto it = free_.emplace(off, sz).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+// Operator identity of a request: the descriptor without its capacity and
+// with an explicit direction table by value.
+struct PlanKey {
+  bz_plan_desc d{};
+  std::vector<double> dirs, weights;
+  bool operator==(const PlanKey& o) const {
+    return d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
+           d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
+           d.a2 == o.d.a2 && d.precision == o.d.precision && d.transform == o.d.transform &&
+           d.project == o.d.project && d.chunks == o.d.chunks && dirs == o.dirs && weights == o.weights;
+  }
+};
+
+PlanKey make_key(const bz_plan_desc& d) {
+  PlanKey k;
+  k.d = d;
+  k.d.max_cells = 0;
+  k.d.dirs = nullptr;
+  k.d.weights = nullptr;
+  if (d.dir_kind == BZ_DIRS_EXPLICIT && d.dirs && d.weights && d.m > 0) {
+    k.dirs.assign(d.dirs, d.dirs + 3 * size_t(d.m));
+    k.weights.assign(d.weights, d.weights + size_t(d.m));
+  }
+  return k;
+}
+
+struct CachedPlan {
+  PlanKey key;
+  bz_plan* plan = nullptr;
+  size_t tables_off = 0, tables_bytes = 0;
+  int inflight = 0;
+  uint64_t last_use = 0;
+};
+
+struct Req {
+  uint64_t ticket = 0;
+  bz_request r{};
+  PlanKey key;
+  int state = BZ_REQ_QUEUED;
+  bz_status err = BZ_OK;
+  uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+  int bypassed = 0;
+  CachedPlan* cp = nullptr;
+  size_t ws_off = 0, ws_bytes = 0;
+  hipEvent_t ev = nullptr;
+};
+
+}  // namespace
+
+struct bz_server {
+  bz_server_desc d{};
+  Arena arena;
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  hipStream_t upload = nullptr;
+  std::vector<hipEvent_t> event_pool;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::vector<uint64_t> inflight;
+  std::vector<std::unique_ptr<CachedPlan>> plans;
+  uint64_t next_ticket = 1;
+  int next_stream = 0;
+  bool stop = false;
+  std::thread th;
+  // statistics
+  std::vector<double> lat_ms;
+  uint64_t submitted = 0, completed = 0, failed = 0, cells_done = 0;
+  uint64_t t_first_submit = 0, t_last_done = 0;
+};
+
+namespace {
+
+void finish(bz_server* s, Req& q, int state, bz_status err) {
+  q.state = state;
+  q.err = err;
+  q.t_done = now_ns();
+  if (state == BZ_REQ_DONE) {
+    s->completed += 1;
+    s->cells_done += uint64_t(q.r.ncells);
+    s->lat_ms.push_back(double(q.t_done - q.t_submit) * 1e-6);
+    s->t_last_done = q.t_done;
+  } else {
+    s->failed += 1;
+  }
+}
+
+hipEvent_t take_event(bz_server* s) {
+  if (!s->event_pool.empty()) {
+    hipEvent_t e = s->event_pool.back();
+    s->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Evict idle cached plans (least recently used first) until `need` bytes can
+// be allocated or nothing idle is left.
+bool alloc_with_eviction(bz_server* s, size_t need, size_t* off) {
+  while (!s->arena.alloc(need, off)) {
+    CachedPlan* victim = nullptr;
+    size_t vi = 0;
+    for (size_t i = 0; i < s->plans.size(); ++i) {
+      CachedPlan* c = s->plans[i].get();
+      if (c->inflight == 0 && (!victim || c->last_use < victim->last_use)) {
+        victim = c;
+        vi = i;
+      }
+    }
+    if (!victim) return false;
+    s->arena.release(victim->tables_off, victim->tables_bytes);
+    bz_plan_destroy(victim->plan);
+    s->plans.erase(s->plans.begin() + long(vi));
+  }
+  return true;
+}
+
+// Find or build the plan of a request (called with the lock held; releases
+// it while the FP64 tables are built).
+CachedPlan* get_plan(bz_server* s, std::unique_lock<std::mutex>& lk, Req& q, bz_status* err) {
+  for (auto& c : s->plans)
+    if (c->key == q.key) return c.get();
+  bz_plan_desc d = q.r.plan;
+  d.max_cells = std::max(1, q.r.ncells);
+  if (q.r.plan.dir_kind == BZ_DIRS_EXPLICIT) {
+    d.dirs = q.key.dirs.data();
+    d.weights = q.key.weights.data();
+  }
+  bz_plan* p = nullptr;
+  lk.unlock();
+  const bz_status st = bz_plan_create(&d, &p);
+  lk.lock();
+  if (st != BZ_OK) {
+    *err = st;
+    return nullptr;
+  }
+  for (auto& c : s->plans)  // built concurrently by nobody else, but be safe
+    if (c->key == q.key) {
+      bz_plan_destroy(p);
+      return c.get();
+    }
+  auto c = std::make_unique<CachedPlan>();
+  c->key = q.key;
+  c->plan = p;
+  c->tables_bytes = p->tables_bytes;
+  if (!alloc_with_eviction(s, c->tables_bytes, &c->tables_off)) {
+    bz_plan_destroy(p);
+    *err = BZ_ERR_NOMEM;
+    return nullptr;
+  }
+  const bz_status up = bz::upload_tables(p, s->arena.base + c->tables_off, s->upload);
+  if (up != BZ_OK) {
+    s->arena.release(c->tables_off, c->tables_bytes);
+    bz_plan_destroy(p);
+    *err = up;
+    return nullptr;
+  }
+  s->plans.push_back(std::move(c));
+  return s->plans.back().get();
+}
+
+void reap(bz_server* s) {
+  for (size_t i = 0; i < s->inflight.size();) {
+    Req& q = s->reqs[s->inflight[i]];
+    const hipError_t e = hipEventQuery(q.ev);
+    if (e == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    s->arena.release(q.ws_off, q.ws_bytes);
+    q.cp->inflight -= 1;
+    s->event_pool.push_back(q.ev);
+    q.ev = nullptr;
+    if (e == hipSuccess) finish(s, q, BZ_REQ_DONE, BZ_OK);
+    else finish(s, q, BZ_REQ_FAILED, BZ_ERR_DEVICE);
+    s->inflight[i] = s->inflight.back();
+    s->inflight.pop_back();
+  }
+}
+
+void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
+  bool blocked = false;  // an earlier request ran out of bypasses
+  for (size_t qi = 0; qi < s->queue.size() && !blocked;) {
+    if (int(s->inflight.size()) >= s->d.max_inflight) return;
+    const uint64_t id = s->queue[qi];
+    Req& q = s->reqs[id];
+    bz_status err = BZ_OK;
+    CachedPlan* cp = get_plan(s, lk, q, &err);
+    if (!cp) {
+      finish(s, q, BZ_REQ_FAILED, err);
+      s->queue.erase(s->queue.begin() + long(qi));
+      continue;
+    }
+    const bz_plan* p = cp->plan;
+    const size_t ws = p->ws_fixed + p->ws_per_cell * size_t(std::max(1, q.r.ncells));
+    if (ws + cp->tables_bytes > s->arena.bytes) {  // can never fit
+      finish(s, q, BZ_REQ_FAILED, BZ_ERR_NOMEM);
+      s->queue.erase(s->queue.begin() + long(qi));
+      continue;
+    }
+    size_t off = 0;
+    cp->inflight += 1;  // pin the plan while allocating
+    const bool ok = alloc_with_eviction(s, ws, &off);
+    cp->inflight -= 1;
+    if (!ok) {
+      q.bypassed += 1;
+      if (q.bypassed > kMaxBypass) blocked = true;
+      ++qi;
+      continue;
+    }
+    hipEvent_t ev = take_event(s);
+    hipStream_t st = s->streams[size_t(s->next_stream)];
+    s->next_stream = (s->next_stream + 1) % int(s->streams.size());
+    const bz::Binding b = bz::make_binding(p, s->arena.base + cp->tables_off, s->arena.base + off, ws);
+    bz_status lst = ev ? BZ_OK : BZ_ERR_DEVICE;
+    if (lst == BZ_OK && q.r.ncells > 0)
+      lst = bz::launch_collide(p, b, q.r.f, q.r.f_dtype == BZ_FP32, q.r.idx, q.r.ncells, nullptr, q.r.q,
+                               (q.r.flags & BZ_SCATTER) != 0, st, false);
+    if (lst == BZ_OK && hipEventRecord(ev, st) != hipSuccess) lst = BZ_ERR_DEVICE;
+    s->queue.erase(s->queue.begin() + long(qi));
+    if (lst != BZ_OK) {
+      s->arena.release(off, ws);
+      if (ev) s->event_pool.push_back(ev);
+      finish(s, q, BZ_REQ_FAILED, lst);
+      continue;
+    }
+    q.state = BZ_REQ_ADMITTED;
+    q.t_admit = now_ns();
+    q.cp = cp;
+    q.ws_off = off;
+    q.ws_bytes = ws;
+    q.ev = ev;
+    cp->inflight += 1;
+    cp->last_use = q.t_admit;
+    s->inflight.push_back(id);
+  }
+}
+
+void scheduler(bz_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    reap(s);
+    admit(s, lk);
+    if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+    if (s->inflight.empty()) {
+      s->cv.wait(lk, [s] { return s->stop || !s->queue.empty(); });
+    } else {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+bz_status bz_server_create(const bz_server_desc* d, bz_server** out) {
+  bz::clear_error();
+  if (!d || !out) return bz::fail(BZ_ERR_ARG, "bz_server_create: null argument");
+  *out = nullptr;
+  if (!d->arena_dev || d->arena_bytes < kAlign) return bz::fail(BZ_ERR_ARG, "bz_server_create: arena missing or too small");
+  if (uintptr_t(d->arena_dev) & (kAlign - 1)) return bz::fail(BZ_ERR_ARG, "bz_server_create: arena must be 256-byte aligned");
+  if (d->max_inflight < 1 || d->n_streams < 1 || d->n_streams > 16 || d->max_queue < 1)
+    return bz::fail(BZ_ERR_ARG, "bz_server_create: need max_inflight >= 1, 1 <= n_streams <= 16, max_queue >= 1");
+  auto s = std::make_unique<bz_server>();
+  s->d = *d;
+  s->arena.init(d->arena_dev, d->arena_bytes);
+  if (hipGetDevice(&s->device) != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_server_create: no device");
+  for (int i = 0; i < d->n_streams + 1; ++i) {
+    hipStream_t st = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      return bz::fail(BZ_ERR_DEVICE, "bz_server_create: %s", hipGetErrorString(e));
+    }
+    if (i < d->n_streams) s->streams.push_back(st);
+    else s->upload = st;
+  }
+  bz_server* raw = s.release();
+  raw->th = std::thread(scheduler, raw);
+  *out = raw;
+  return BZ_OK;
+}
+
+bz_status bz_serve_submit(bz_server* s, const bz_request* r, uint64_t* ticket) {
+  bz::clear_error();
+  if (!s || !r || !ticket) return bz::fail(BZ_ERR_ARG, "bz_serve_submit: null argument");
+  if (r->ncells < 0) return bz::fail(BZ_ERR_ARG, "bz_serve_submit: ncells < 0");
+  if (r->ncells > 0 && (!r->f || !r->q)) return bz::fail(BZ_ERR_ARG, "bz_serve_submit: null f or q");
+  if (r->f_dtype != BZ_FP32 && r->f_dtype != BZ_FP64) return bz::fail(BZ_ERR_ARG, "bz_serve_submit: bad f_dtype");
+  if ((r->flags & BZ_SCATTER) && !r->idx) return bz::fail(BZ_ERR_ARG, "bz_serve_submit: BZ_SCATTER needs idx");
+  if (r->plan.dir_kind == BZ_DIRS_EXPLICIT && (!r->plan.dirs || !r->plan.weights || r->plan.m < 1 || r->plan.m > 512))
+    return bz::fail(BZ_ERR_ARG, "bz_serve_submit: explicit rule needs dirs and weights");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->stop) return bz::fail(BZ_ERR_STATE, "bz_serve_submit: server is shutting down");
+  if (int(s->queue.size()) >= s->d.max_queue) return BZ_AGAIN;
+  Req q;
+  q.ticket = s->next_ticket++;
+  q.r = *r;
+  q.key = make_key(r->plan);
+  q.t_submit = now_ns();
+  if (s->submitted == 0) s->t_first_submit = q.t_submit;
+  s->submitted += 1;
+  *ticket = q.ticket;
+  s->queue.push_back(q.ticket);
+  s->reqs.emplace(q.ticket, std::move(q));
+  s->cv.notify_one();
+  return BZ_OK;
+}
+
+bz_status bz_serve_poll(bz_server* s, uint64_t ticket, bz_result* out) {
+  bz::clear_error();
+  if (!s || !out) return bz::fail(BZ_ERR_ARG, "bz_serve_poll: null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return bz::fail(BZ_ERR_ARG, "bz_serve_poll: unknown or already collected ticket %llu", (unsigned long long)ticket);
+  const Req& q = it->second;
+  out->state = q.state;
+  out->err = q.err;
+  out->t_submit_ns = q.t_submit;
+  out->t_admit_ns = q.t_admit;
+  out->t_done_ns = q.t_done;
+  if (q.state == BZ_REQ_DONE || q.state == BZ_REQ_FAILED) {
+    s->reqs.erase(it);
+    return BZ_OK;
+  }
+  return BZ_AGAIN;
+}
+
+bz_status bz_server_stats(bz_server* s, bz_server_stats_t* out) {
+  bz::clear_error();
+  if (!s || !out) return bz::fail(BZ_ERR_ARG, "bz_server_stats: null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  std::memset(out, 0, sizeof *out);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->queued = int32_t(s->queue.size());
+  out->inflight = int32_t(s->inflight.size());
+  out->plans_cached = int32_t(s->plans.size());
+  out->arena_used = s->arena.used;
+  out->arena_peak = s->arena.peak;
+  if (!s->lat_ms.empty()) {
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t i = size_t(std::min<double>(double(v.size() - 1), std::ceil(p * double(v.size())) - 1.0));
+      return v[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+  }
+  if (s->t_last_done > s->t_first_submit)
+    out->cells_per_s = double(s->cells_done) / (double(s->t_last_done - s->t_first_submit) * 1e-9);
+  return BZ_OK;
+}
+
+bz_status bz_server_destroy(bz_server* s) {
+  bz::clear_error();
+  if (!s) return BZ_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (auto& c : s->plans) bz_plan_destroy(c->plan);
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
+  for (auto x : s->streams) (void)hipStreamDestroy(x);
+  if (s->upload) (void)hipStreamDestroy(s->upload);
+  delete s;
+  return BZ_OK;
+}
+
+}  // extern "C"

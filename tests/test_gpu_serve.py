@@ -1,0 +1,128 @@
+"""GPU tests of the serving runtime (bz_server_* / bz_serve_*): requests from
+several client threads with different grid sizes and cell counts; results are
+bitwise equal to a direct bz_collide_batch of the same operator, and a
+request's result is the same alone and in the mix; admission never exceeds
+the arena; failed requests do not disturb the others."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import bz_inputs as gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def plan(bz, n, m=8, precision=1):
+    return bz.make_plan_desc(n=n, L=8.0, m=m, dir_kind=bz.BZ_DIRS_SPIRAL, precision=precision)
+
+
+def wait(srv, ticket, timeout=60.0):
+    t0 = time.time()
+    while True:
+        done, res = srv.poll(ticket)
+        if done:
+            return res
+        assert time.time() - t0 < timeout, "request did not finish"
+        time.sleep(0.0005)
+
+
+def inputs(n, cells, seed):
+    return torch.from_numpy(gen.bimaxwellian_batch(cells, n, 8.0, seed=seed)).cuda()
+
+
+def test_serve_matches_direct_and_mix():
+    import paper_2505_03360_amd as bz
+    print("case serve mix", flush=True)
+    srv = bz.Server(arena_bytes=2 << 30, max_inflight=6, n_streams=3)
+    work = [(16, 5, 1), (24, 3, 2), (32, 4, 3), (16, 37, 4), (32, 9, 5), (24, 11, 6)]
+    fs = {k: inputs(n, c, s) for k, (n, c, s) in enumerate(work)}
+    # alone: one request at a time
+    alone = {}
+    for k, (n, c, s) in enumerate(work):
+        q = torch.empty((c, n, n, n), dtype=torch.float64, device="cuda")
+        res = wait(srv, srv.submit(fs[k], q, plan(bz, n)))
+        assert res.state == bz.BZ_REQ_DONE and res.err == 0
+        assert res.t_submit_ns <= res.t_admit_ns <= res.t_done_ns
+        alone[k] = q.clone()
+    # in the mix: all requests from three client threads at once, twice each
+    outs = {}
+
+    def client(keys):
+        tickets = []
+        for k in keys:
+            n, c, _ = work[k]
+            for r in range(2):
+                q = torch.empty((c, n, n, n), dtype=torch.float64, device="cuda")
+                outs[(k, r)] = q
+                tickets.append(srv.submit(fs[k], q, plan(bz, n), client_id=k))
+        for t in tickets:
+            res = wait(srv, t)
+            assert res.state == bz.BZ_REQ_DONE, res.err
+    th = [threading.Thread(target=client, args=(ks,)) for ks in ([0, 3], [1, 4], [2, 5])]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    for (k, r), q in outs.items():
+        assert torch.equal(q, alone[k]), (k, r)
+    # and equal to a direct call of the same operator
+    for k, (n, c, s) in enumerate(work):
+        col = bz.Collider(n, c, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=1)
+        assert torch.equal(col(fs[k]), alone[k])
+    st = srv.stats()
+    assert st.completed == 18 and st.failed == 0 and st.p99_ms >= st.p50_ms > 0
+    srv.close()
+
+
+def test_admission_bounded_by_arena():
+    import paper_2505_03360_amd as bz
+    print("case serve arena", flush=True)
+    n, cells = 32, 16
+    pd = plan(bz, n)
+    p = bz.bz_plan_create(bz.make_plan_desc(n=n, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=1))
+    tb, fixed, per = bz.bz_plan_device_bytes(p)
+    bz.bz_plan_destroy(p)
+    arena = tb + 2 * (fixed + per * cells) + 4096  # tables + two requests
+    srv = bz.Server(arena_bytes=arena, max_inflight=8, n_streams=4)
+    f = inputs(n, cells, 7)
+    qs = [torch.empty((cells, n, n, n), dtype=torch.float64, device="cuda") for _ in range(10)]
+    ts = [srv.submit(f, q, pd) for q in qs]
+    for t in ts:
+        assert wait(srv, t).state == bz.BZ_REQ_DONE
+    st = srv.stats()
+    assert st.arena_peak <= arena
+    for q in qs[1:]:
+        assert torch.equal(q, qs[0])
+    srv.close()
+
+
+def test_failed_requests_are_isolated():
+    import paper_2505_03360_amd as bz
+    print("case serve failures", flush=True)
+    srv = bz.Server(arena_bytes=512 << 20, max_inflight=4, n_streams=2)
+    f = inputs(16, 4, 8)
+    good = torch.empty((4, 16, 16, 16), dtype=torch.float64, device="cuda")
+    bad_n = bz.make_plan_desc(n=20, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL)
+    t_bad = srv.submit(f, good, bad_n)
+    huge = torch.empty(1, dtype=torch.float64, device="cuda")
+    t_huge = srv.submit(f, huge, plan(bz, 16), ncells=400000)  # can never fit the arena
+    t_good = srv.submit(f, good, plan(bz, 16))
+    r_bad, r_huge, r_good = wait(srv, t_bad), wait(srv, t_huge), wait(srv, t_good)
+    assert r_bad.state == bz.BZ_REQ_FAILED and r_bad.err == bz.BZ_ERR_UNSUPPORTED
+    assert r_huge.state == bz.BZ_REQ_FAILED and r_huge.err == bz.BZ_ERR_NOMEM
+    assert r_good.state == bz.BZ_REQ_DONE
+    with pytest.raises(bz.BzError):
+        srv.poll(t_good)  # already collected
+    st = srv.stats()
+    assert st.failed == 2 and st.completed == 1
+    srv.close()
