@@ -110,7 +110,8 @@ def serving_run(seconds: float, seed: int = 5):
             n = int(rng.choice(sizes))
             k = int(np.clip(rng.poisson(512), 16, 4096))
             if len(out) == 2:
-                r, kk = wait(out.pop(0))
+                t_old, kk = out.pop(0)
+                r = wait(t_old)
                 with lock:
                     if r.state == bz.BZ_REQ_DONE:
                         lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
@@ -118,13 +119,19 @@ def serving_run(seconds: float, seed: int = 5):
                     else:
                         failed[0] += 1
             t = srv.submit(pool[n][:k], bufs[n][slot][:k], plans[n], client_id=cid)
+            if t is None:  # queue full: retry later
+                time.sleep(0.0005)
+                continue
             slot ^= 1
             out.append((t, k))
         for t, kk in out:
             r = wait(t)
             with lock:
-                lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
-                cells[0] += kk
+                if r.state == bz.BZ_REQ_DONE:
+                    lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+                    cells[0] += kk
+                else:
+                    failed[0] += 1
     t0 = time.perf_counter()
     th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
     for t in th:

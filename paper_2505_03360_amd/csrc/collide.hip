@@ -223,6 +223,14 @@ __device__ __forceinline__ gptr<T> opaque_global(const T* p) {
   return (gptr<T>)p;
 }
 
+// Workgroup barrier that orders LDS traffic only: global loads issued before
+// it stay in flight (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct FusedArgs {
   int ncells;
   const int32_t* ncells_dev;
@@ -266,74 +274,68 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   // flight), transformed, and its slice-0 outputs go to LDS at once; the
   // other slices stay in registers until their turn.
   cx<float> rest[S > 1 ? S : 1][S > 1 ? N - W : 1];
-  __syncthreads();  // LDS free: the previous pass's stage C has read it
+  lds_barrier();  // LDS free: the previous pass's stage C has read it
   if constexpr (S == 2) {
-    // Mirror pairing: thread (k1, k2), k2 < N/2, loads pencil (k1, k2, :) and
-    // also forms its mirror (-k1, -k2, :): the multipliers are even and fhat
-    // of a real f is Hermitian, so X(-k1,-k2,k3) = M(k1,k2,-k3) conj(F(k1,k2,-k3)).
-    // Row k2 = 0 is its own mirror row; its threads take row N/2 instead,
-    // which is zero in the gain passes (the multipliers vanish on the Nyquist
-    // planes) and loaded directly in the loss pass.
+    // Mirror pairing.  With M = a + ib (a, b real and even in k) and F of a
+    // real f (Hermitian), thread (k1, k2), k2 < N/2, transforms U = a F and
+    // V = b F along k3 once; then pencil (k1, k2) is IDFT(X) = U^ + i V^ and
+    // its mirror (-k1, -k2), whose X(k3) = M(-k3) conj(F(-k3)), is
+    // conj(U^) + i conj(V^).  One set of loads and two transforms give both.
+    // Row k2 = 0 mirrors onto itself: its threads take row N/2 instead, which
+    // is zero in the gain passes (the multipliers vanish on the Nyquist
+    // planes) and transformed directly in the loss pass.
     const int k1 = t % N, k2 = t / N;
     const bool row0 = k2 == 0;
     const int k1b = row0 ? k1 : (N - k1) % N;
     const int k2b = row0 ? N / 2 : N - k2;
     const size_t off = size_t(k2) * N * N + k1;
-    const gptr<cx<float>> fb = opaque_global(fhc + off);
-    const gptr<cx<float>> mb = opaque_global(mp + off);
+    cx<float> u[N], v[N];
     {
-      // pencil (k1, k2): X = M F
-      cx<float> xa[N];
+      const gptr<cx<float>> fb = opaque_global(fhc + off);
+      const gptr<cx<float>> mb = opaque_global(mp + off);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
           const cx<float> F = fb[k3 * N], Mu = mb[k3 * N];
-          xa[k3] = {Mu.x * F.x - Mu.y * F.y, Mu.x * F.y + Mu.y * F.x};
+          u[k3] = {Mu.x * F.x, Mu.x * F.y};
+          v[k3] = {Mu.y * F.x, Mu.y * F.y};
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      bzk::fft<N, 1>(xa);
-#pragma unroll
-      for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = xa[j];
-#pragma unroll
-      for (int j = W; j < N; ++j) rest[0][j - W] = xa[j];
     }
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      // mirror pencil (-k1, -k2): X(k3) = M(-k3) conj(F(-k3)), the same lines
-      // re-read (cache hits) so that only one pencil is live at a time
-      cx<float> xb[N];
+    bzk::fft<N, 1>(u);
+    bzk::fft<N, 1>(v);
+    cx<float> xr[LOSS ? N : 1];  // loss pass: row N/2 pencil of the row-0 threads
+    if constexpr (LOSS) {
       if (row0) {
-        if constexpr (LOSS) {
-          const gptr<cx<float>> fr = opaque_global(fhc + size_t(N / 2) * N * N + k1);
-          const gptr<cx<float>> mr = opaque_global(mp + size_t(N / 2) * N * N + k1);
+        const gptr<cx<float>> fr = opaque_global(fhc + size_t(N / 2) * N * N + k1);
+        const gptr<cx<float>> mr = opaque_global(mp + size_t(N / 2) * N * N + k1);
 #pragma unroll
-          for (int k3 = 0; k3 < N; ++k3) {
-            const cx<float> F = fr[k3 * N], Mu = mr[k3 * N];
-            xb[k3] = {Mu.x * F.x - Mu.y * F.y, Mu.x * F.y + Mu.y * F.x};
-          }
-        } else {
-#pragma unroll
-          for (int k3 = 0; k3 < N; ++k3) xb[k3] = {0.0f, 0.0f};
+        for (int k3 = 0; k3 < N; ++k3) {
+          const cx<float> F = fr[k3 * N], Mv = mr[k3 * N];
+          xr[k3] = {Mv.x * F.x - Mv.y * F.y, Mv.x * F.y + Mv.y * F.x};
         }
-      } else {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-          for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
-            const int m3 = (N - k3) % N;
-            const cx<float> F = fb[m3 * N], Mu = mb[m3 * N];
-            xb[k3] = {Mu.x * F.x + Mu.y * F.y, Mu.y * F.x - Mu.x * F.y};  // (a + ib) conj(F)
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        bzk::fft<N, 1>(xr);
       }
-      bzk::fft<N, 1>(xb);
+    }
+    auto out_b = [&](int j) -> cx<float> {
+      if constexpr (LOSS) {
+        if (row0) return xr[j];
+      } else {
+        if (row0) return cx<float>{0.0f, 0.0f};
+      }
+      return cx<float>{u[j].x + v[j].y, v[j].x - u[j].y};
+    };
 #pragma unroll
-      for (int j = 0; j < W; ++j) lds[(k2b * N + k1b) * AB + j] = xb[j];
+    for (int j = 0; j < W; ++j) {
+      lds[(k2 * N + k1) * AB + j] = cx<float>{u[j].x - v[j].y, u[j].y + v[j].x};
+      lds[(k2b * N + k1b) * AB + j] = out_b(j);
+    }
 #pragma unroll
-      for (int j = W; j < N; ++j) rest[1][j - W] = xb[j];
+    for (int j = W; j < N; ++j) {
+      rest[0][j - W] = cx<float>{u[j].x - v[j].y, u[j].y + v[j].x};
+      rest[1][j - W] = out_b(j);
     }
   } else {
 #pragma unroll
@@ -369,7 +371,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     if (s > 0) {
-      __syncthreads();  // stage C of the previous slice has read the LDS
+      lds_barrier();  // stage C of the previous slice has read the LDS
 #pragma unroll
       for (int q = 0; q < S; ++q) {
         int k1, k2;
@@ -386,18 +388,25 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
         for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = rest[q][(s - 1) * W + j];
       }
     }
-    __syncthreads();
+    lds_barrier();
     cx<float> rb[N];
+    // read in the order the transform consumes its inputs (first sub-transform first)
 #pragma unroll
-    for (int k2 = 0; k2 < N; ++k2) rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
+    for (int r = 0; r < N; ++r) {
+      const int k2 = bzk::first_stage_order<N>(r);
+      rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
+    }
     bzk::fft<N, 1>(rb);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int j2 = 0; j2 < N; ++j2) lds[(j2 * N + tb_k1) * W + tl] = rb[j2];
-    __syncthreads();
+    lds_barrier();
     cx<float> rc[N];
 #pragma unroll
-    for (int k1 = 0; k1 < N; ++k1) rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
+    for (int r = 0; r < N; ++r) {
+      const int k1 = bzk::first_stage_order<N>(r);
+      rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
+    }
     bzk::fft<N, 1>(rc);
     if constexpr (LOSS) {
       // acc -= (sL f - Im) Re with the exact input f
@@ -475,11 +484,11 @@ __global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
       for (int o = 32; o > 0; o >>= 1) m[k] += __shfl_xor(m[k], o);
     constexpr int NW = (N * N / S) / 64;
     double* red = reinterpret_cast<double*>(lds);
-    __syncthreads();  // the last pass's stage C has read the LDS
+    lds_barrier();  // the last pass's stage C has read the LDS
     if ((t & 63) == 0)
 #pragma unroll
       for (int k = 0; k < 5; ++k) red[k * NW + t / 64] = m[k];
-    __syncthreads();
+    lds_barrier();
     double lam[5];
     {
       double tot[5];

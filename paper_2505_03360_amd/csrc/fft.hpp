@@ -192,4 +192,21 @@ BZK_HD void fft(cx<T> (&x)[N]) {
   }
 }
 
+// The r-th input the transform's first stage consumes: fft_ct<N1, N2> first
+// transforms the N1 subsequences x[n1 + N1 n2] (n1 = 0, 1, ...), so reading
+// inputs in this order lets the first sub-transform start before the last
+// input arrives.
+template <int N>
+constexpr int first_stage_order(int r) {
+  if constexpr (N % 3 == 0 && N > 3) {
+    return (r % (N / 3)) * 3 + r / (N / 3);
+  } else if constexpr (N == 8) {
+    return (r % 4) * 2 + r / 4;
+  } else if constexpr (N % 4 == 0 && N > 4) {
+    return (r % (N / 4)) * 4 + r / (N / 4);
+  } else {
+    return r;
+  }
+}
+
 }  // namespace bzk
