@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 N, M, CELLS, L = 32, 32, 256, 8.0
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, published
 PEAK_FP64_TFLOPS = 78.6
+# HBM-side bytes per launch of k_collide_fused<32,2> on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain
+# 256 MiB copy needs); set to None whenever the kernel changes until re-measured.
+FUSED_TRAFFIC_BYTES = (228872 * 2.0 + 124019 * 1.0) * 1024
 
 
 def algorithmic_flops(n: int, m: int):
@@ -239,7 +243,7 @@ def main():
                                "R=(sqrt2-1)L, FP32 fused + FP64 projection, f FP64 resident",
                    "cells": CELLS, "n": N, "m": M},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": FUSED_TRAFFIC_BYTES,
                      "kernel": "k_collide_fused<32,2>",
                      "kernel_ms": stage_ms[1], "algorithmic_flops_per_launch": kern_flops * CELLS},
         "stages_ms": {"forward": stage_ms[0], "directions": stage_ms[1], "projection": stage_ms[2],

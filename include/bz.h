@@ -95,6 +95,8 @@ typedef struct {
                             0: raw Q in the plan precision */
   int32_t max_cells;     /* largest batch the bound workspace must hold */
   int32_t chunks;        /* fused path: direction chunks per cell (0 = auto) */
+  int32_t slices;        /* fused path: j3 slices of the LDS transposes, 1 or 2
+                            (n = 16 only; n = 32 always uses 2); 0 = auto */
 } bz_plan_desc;
 
 typedef struct bz_plan bz_plan;
@@ -141,6 +143,18 @@ bz_status bz_plan_capacity(const bz_plan* plan, int32_t* cells);
 
 /* Evaluation strategy the plan resolved to (BZ_XF_FUSED or BZ_XF_PLAIN). */
 bz_status bz_plan_transform(const bz_plan* plan, int32_t* transform);
+
+/* Strategy table written by the autotuner (paper_2505_03360_amd/autotune.py):
+   one line per tuned case, "gfx950 n m precision max_cells transform chunks
+   slices us_per_cell".  bz_plan_create consults it when desc.transform is
+   BZ_XF_AUTO and desc.chunks and desc.slices are 0: it takes the line with the
+   same (n, m, precision) and the largest max_cells not above the plan's (else
+   the smallest).  NULL clears it.  The environment variable BZ_TUNE_TABLE
+   names a table when none is set. */
+bz_status bz_set_tune_table(const char* path);
+
+/* Strategy the plan resolved to: transform, chunks, slices. */
+bz_status bz_plan_strategy(const bz_plan* plan, int32_t* transform, int32_t* chunks, int32_t* slices);
 
 /* Host copies of the plan's direction rule: dirs [m][3], weights [m]. */
 bz_status bz_plan_get_rule(const bz_plan* plan, double* dirs, double* weights);

@@ -46,6 +46,7 @@ class BzPlanDesc(ctypes.Structure):
         ("project", ctypes.c_int32),
         ("max_cells", ctypes.c_int32),
         ("chunks", ctypes.c_int32),
+        ("slices", ctypes.c_int32),
     ]
 
 
@@ -114,6 +115,8 @@ SIGNATURES = [
     ("bz_plan_destroy", _I32, [_VP]),
     ("bz_plan_capacity", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("bz_plan_transform", _I32, [_VP, ctypes.POINTER(_I32)]),
+    ("bz_set_tune_table", _I32, [ctypes.c_char_p]),
+    ("bz_plan_strategy", _I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("bz_plan_get_rule", _I32, [_VP, _c_double_p, _c_double_p]),
     ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
     ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
@@ -165,11 +168,12 @@ def bz_last_error() -> str:
 def make_plan_desc(n: int, L: float = 8.0, R: float = 0.0, gamma: float = 1.0, kernel_c: float = 4.0,
                    m: int = 6, dir_kind: int = BZ_DIRS_ICOSA6, dirs=None, weights=None, a1: int = 0,
                    a2: int = 0, precision: int = BZ_FP32, transform: int = BZ_XF_AUTO, project: int = 1,
-                   max_cells: int = 1, chunks: int = 0) -> BzPlanDesc:
+                   max_cells: int = 1, chunks: int = 0, slices: int = 0) -> BzPlanDesc:
     d = BzPlanDesc()
     d.n, d.L, d.R, d.gamma, d.kernel_c = n, L, R, gamma, kernel_c
     d.m, d.dir_kind, d.a1, d.a2 = m, dir_kind, a1, a2
     d.precision, d.transform, d.project, d.max_cells, d.chunks = precision, transform, project, max_cells, chunks
+    d.slices = slices
     d._keep = []
     if dirs is not None:
         import numpy as np
@@ -213,6 +217,16 @@ def bz_plan_transform(plan: int) -> int:
     c = _I32()
     _check(lib().bz_plan_transform(plan, ctypes.byref(c)))
     return c.value
+
+
+def bz_set_tune_table(path) -> None:
+    _check(lib().bz_set_tune_table(None if path is None else str(path).encode()))
+
+
+def bz_plan_strategy(plan: int):
+    t, c, s = _I32(), _I32(), _I32()
+    _check(lib().bz_plan_strategy(plan, ctypes.byref(t), ctypes.byref(c), ctypes.byref(s)))
+    return t.value, c.value, s.value
 
 
 def bz_plan_get_rule(plan: int, m: int):

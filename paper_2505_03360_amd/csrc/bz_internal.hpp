@@ -45,6 +45,7 @@ struct bz_plan {
   int project = 1;
   int transform = BZ_XF_PLAIN;  // resolved strategy
   int chunks = 1;               // direction chunks per cell (fused path)
+  int slices = 2;               // j3 slices of the fused kernel's transposes
   std::vector<double> dirs;     // [m][3]
   std::vector<double> w;        // [m]
   // FP64 host tables in device layout [p][k2][k3][k1] x (a, a'), p < m1;
@@ -79,5 +80,6 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
 Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
 bool fused_supported(int n, int fp32);
+bool fused_slices_supported(int n, int slices);
 int fused_default_chunks(int n);
 }  // namespace bz

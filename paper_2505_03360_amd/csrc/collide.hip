@@ -436,8 +436,13 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 //            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
 // LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
 // lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
+// Register budget: the paired (S = 2) kernels need up to 256 VGPRs (2 waves
+// per SIMD); N = 16 with one slice fits 4 waves per SIMD (128 VGPRs).
 template <int N, int S>
-__global__ __launch_bounds__(N * N / S) void k_collide_fused(FusedArgs a) {
+constexpr int fused_min_waves() { return (N <= 16 && S == 1) ? 4 : 2; }
+
+template <int N, int S>
+__global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collide_fused(FusedArgs a) {
   constexpr int W = N / S;
   constexpr int AB = W + 1;
   __shared__ cx<float> lds[N * N * AB];
@@ -677,6 +682,8 @@ namespace bz {
 
 bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
 
+bool fused_slices_supported(int n, int slices) { return (n == 16 && (slices == 1 || slices == 2)) || (n == 32 && slices == 2); }
+
 int fused_default_chunks(int n) { return 1; }
 
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
@@ -748,7 +755,8 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fa.q = static_cast<double*>(q);
       fused_projection = fa.fuse_project != 0;
       if (p->n == 32) launch_fused<32, 2>(fa, ncells, s);
-      else if (p->n == 16) launch_fused<16, 1>(fa, ncells, s);
+      else if (p->n == 16 && p->slices == 1) launch_fused<16, 1>(fa, ncells, s);
+      else if (p->n == 16) launch_fused<16, 2>(fa, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
     } else {
       st = run_plain<float>(p, a, ncells, s, false, timed);

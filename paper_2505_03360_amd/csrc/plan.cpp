@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "bz_internal.hpp"
@@ -262,6 +264,57 @@ bool build_gram_inverse(bz_plan* p) {
   return spd_inverse5(G, p->ginv);
 }
 
+// ---------------------------------------------------------------- tune table
+std::mutex g_tune_mu;
+std::string g_tune_path;
+bool g_tune_set = false;
+
+struct TuneChoice {
+  int transform = 0, chunks = 0, slices = 0;
+  bool found = false;
+};
+
+TuneChoice tune_lookup(int n, int m, int precision, int max_cells) {
+  std::string path;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_tune_set) path = g_tune_path;
+  }
+  if (path.empty()) {
+    const char* env = std::getenv("BZ_TUNE_TABLE");
+    if (env) path = env;
+  }
+  TuneChoice best;
+  if (path.empty()) return best;
+  FILE* fp = std::fopen(path.c_str(), "r");
+  if (!fp) return best;
+  char line[512];
+  int best_cells = -1, smallest_cells = 1 << 30;
+  TuneChoice smallest;
+  while (std::fgets(line, sizeof line, fp)) {
+    char arch[64];
+    int tn, tm, tp, tc, tx, tch, ts;
+    double us;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %lf", arch, &tn, &tm, &tp, &tc, &tx, &tch, &ts, &us) != 9) continue;
+    if (std::strcmp(arch, "gfx950") != 0 || tn != n || tm != m || tp != precision) continue;
+    TuneChoice c;
+    c.transform = tx;
+    c.chunks = tch;
+    c.slices = ts;
+    c.found = true;
+    if (tc <= max_cells && tc > best_cells) {
+      best_cells = tc;
+      best = c;
+    }
+    if (tc < smallest_cells) {
+      smallest_cells = tc;
+      smallest = c;
+    }
+  }
+  std::fclose(fp);
+  return best.found ? best : smallest;
+}
+
 void layout(bz_plan* p) {
   const size_t n3 = size_t(p->n) * p->n * p->n;
   const size_t es = p->fp32 ? 4 : 8;
@@ -348,6 +401,7 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   if (d.transform < BZ_XF_AUTO || d.transform > BZ_XF_PLAIN) return fail(BZ_ERR_ARG, "bz_plan_create: bad transform");
   if (d.max_cells < 1) return fail(BZ_ERR_ARG, "bz_plan_create: max_cells must be >= 1");
   if (d.chunks < 0 || d.chunks > d.m + 1) return fail(BZ_ERR_ARG, "bz_plan_create: chunks must be in 0..m+1");
+  if (d.slices < 0 || d.slices > 2) return fail(BZ_ERR_ARG, "bz_plan_create: slices must be 0, 1 or 2");
 
   bz_plan* p = new bz_plan();
   p->d = d;
@@ -400,9 +454,23 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
     delete p;
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel for n=%d precision=%s", d.n, p->fp32 ? "fp32" : "fp64");
   }
-  p->transform = (d.transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
-  p->chunks = p->transform == BZ_XF_FUSED ? (d.chunks > 0 ? d.chunks : fused_default_chunks(p->n)) : 1;
+  int transform = d.transform, chunks = d.chunks, slices = d.slices;
+  if (transform == BZ_XF_AUTO && chunks == 0 && slices == 0) {
+    const TuneChoice tc = tune_lookup(d.n, d.m, d.precision, d.max_cells);
+    if (tc.found && (tc.transform == BZ_XF_PLAIN || (fused_ok && fused_slices_supported(d.n, tc.slices)))) {
+      transform = tc.transform;
+      chunks = tc.chunks;
+      slices = tc.slices;
+    }
+  }
+  p->transform = (transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
+  p->chunks = p->transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(p->n)) : 1;
   if (p->chunks > p->m1) p->chunks = p->m1;
+  p->slices = slices > 0 ? slices : 2;
+  if (p->transform == BZ_XF_FUSED && !fused_slices_supported(p->n, p->slices)) {
+    delete p;
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel with %d slices for n=%d", slices, d.n);
+  }
   build_tables(p);
   if (!build_gram_inverse(p)) { delete p; return fail(BZ_ERR_NUMERIC, "bz_plan_create: Gram matrix not positive definite"); }
   layout(p);
@@ -457,6 +525,23 @@ bz_status bz_plan_transform(const bz_plan* p, int32_t* transform) {
   clear_error();
   if (!p || !transform) return fail(BZ_ERR_ARG, "bz_plan_transform: null argument");
   *transform = p->transform;
+  return BZ_OK;
+}
+
+bz_status bz_set_tune_table(const char* path) {
+  clear_error();
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_set = path != nullptr;
+  g_tune_path = path ? path : "";
+  return BZ_OK;
+}
+
+bz_status bz_plan_strategy(const bz_plan* p, int32_t* transform, int32_t* chunks, int32_t* slices) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_plan_strategy: null plan");
+  if (transform) *transform = p->transform;
+  if (chunks) *chunks = p->chunks;
+  if (slices) *slices = p->slices;
   return BZ_OK;
 }
 
