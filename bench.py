@@ -153,6 +153,65 @@ def serving_run(seconds: float, seed: int = 5):
                         "FP32 + FP64 projection, 16 GiB arena"}
 
 
+def sweep(cells: int = 1024, reps: int = 3):
+    """Precision sweep: N in {32, 48}, M in {32, 64}, gamma in {0, 0.5, 1};
+    FP32 (fused at N=32, plain passes at N=48) and FP64 plain on the same
+    cells (64 seeded shock cells tiled to `cells`).  Reports time per batch,
+    FP32 error against FP64 (per cell and batch, relative L2), and the moment
+    drift max_i |C_i Q| / sum_j |C_ij Q_j| of the raw (unprojected) FP32 output
+    and of the projected one."""
+    import numpy as np
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    out = []
+    for n in (32, 48):
+        base = torch.from_numpy(gen.shock_batch(64, n, L, seed=4)).cuda()
+        f = base.repeat(cells // 64, 1, 1, 1).contiguous()
+        v = (torch.arange(n, dtype=torch.float64, device="cuda") - n // 2) * (2 * L / n)
+        V1, V2, V3 = torch.meshgrid(v, v, v, indexing="ij")
+        C = torch.stack([torch.ones_like(V1), V1, V2, V3, V1 * V1 + V2 * V2 + V3 * V3]).reshape(5, -1)
+
+        def drift(q):
+            qq = q.reshape(q.shape[0], -1)
+            num = (qq @ C.T).abs()
+            den = qq.abs() @ C.abs().T
+            return float((num / den).max())
+        for m in (32, 64):
+            for gamma in (0.0, 0.5, 1.0):
+                rec = {"n": n, "m": m, "gamma": gamma, "cells": cells}
+                res = {}
+                for name, prec, proj in (("fp32", bz.BZ_FP32, 1), ("fp64", bz.BZ_FP64, 1), ("fp32_raw", bz.BZ_FP32, 0)):
+                    col = bz.Collider(n, cells, L=L, m=m, dir_kind=bz.BZ_DIRS_SPIRAL, gamma=gamma, precision=prec,
+                                      project=proj)
+                    q = col(f)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        col(f, out=q)
+                    torch.cuda.synchronize()
+                    res[name] = q
+                    rec[f"{name}_ms_per_batch"] = 1e3 * (time.perf_counter() - t0) / reps
+                    rec[f"{name}_transform"] = "fused" if col.transform == bz.BZ_XF_FUSED else "plain"
+                    col.close()
+                d = (res["fp32"] - res["fp64"]).reshape(cells, -1)
+                per = torch.linalg.vector_norm(d, dim=1) / torch.linalg.vector_norm(res["fp64"].reshape(cells, -1), dim=1)
+                rec["fp32_vs_fp64_batch_rel_l2"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(res["fp64"]))
+                rec["fp32_vs_fp64_median_cell"] = float(per.median())
+                rec["moment_drift_raw_fp32"] = drift(res["fp32_raw"].double())
+                rec["moment_drift_projected_fp32"] = drift(res["fp32"])
+                rec["moment_drift_projected_fp64"] = drift(res["fp64"])
+                rec["fp32_cells_per_s"] = cells / (rec["fp32_ms_per_batch"] * 1e-3)
+                rec["fp64_cells_per_s"] = cells / (rec["fp64_ms_per_batch"] * 1e-3)
+                del res
+                torch.cuda.empty_cache()
+                print(json.dumps(rec), flush=True)
+                out.append(rec)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +220,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run length (0 = skip)")
+    ap.add_argument("--sweep", action="store_true", help="run the precision sweep instead (one JSON line per case)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -176,6 +236,9 @@ def main():
     import paper_2505_03360_amd as bz
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        sweep()
+        return
     f_np = gen.shock_batch(CELLS, N, L, seed=2)
     f = torch.from_numpy(f_np).cuda()
     stream = torch.cuda.current_stream()
