@@ -252,6 +252,98 @@ struct FusedArgs {
   double* q;
 };
 
+// ------------------------------------------------------------------ fused forward
+struct FwdArgs {
+  int ncells;
+  const int32_t* ncells_dev;
+  const void* f;
+  int f_fp32;
+  const int32_t* idx;
+  cx<float>* fh;  // [cell][k2][k3][k1]
+  size_t fh_stride;
+  int mirror;  // also write rows k2 in (N/2, N) (consumers that read every row)
+};
+
+// Forward transform fhat = DFT(f) / N^3 of one cell per workgroup, FP32,
+// N^2/2 threads, everything between the load of f and the write of fhat on
+// chip.
+//   stage 1: thread (i1 < N/2, i3) transforms z(i2) = f[i1][i2][i3] +
+//            i f[i1 + N/2][i2][i3] along i2; f is real, so the two transforms
+//            follow from Z(k2) and conj Z(-k2).  Only k2 in [0, N/2] is kept:
+//            fhat(-k) = conj fhat(k) gives the other rows.
+//   stage 2: pencils along i1 at (k2, i3), in place in LDS.
+//   stage 3: pencils along i3 at (k2, k1); scaled, written to fhat[k2][k3][k1]
+//            (lanes on k1); with `mirror`, rows N - k2 (0 < k2 < N/2) are
+//            written as conj fhat(-k1, k2, -k3).
+// LDS [k2 in 0..N/2][i1, then k1][i3] with row pitch N + 1 (stage 3 reads with
+// lanes on k1 and lands on distinct banks).
+template <int N>
+__global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
+  constexpr int T = N * N / 2, H = N / 2, P = N + 1;
+  __shared__ cx<float> lds[(H + 1) * N * P];
+  const int cell = blockIdx.x;
+  if (cell >= live_count(a.ncells, a.ncells_dev)) return;
+  const int t = threadIdx.x;
+  const long row = a.idx ? long(a.idx[cell]) : long(cell);
+  {
+    const int i3 = t % N, i1 = t / N;
+    const size_t base = size_t(row) * N * N * N + size_t(i1) * N * N + i3;
+    cx<float> z[N];
+    if (a.f_fp32) {
+      const float* f = static_cast<const float*>(a.f) + base;
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) z[i2] = {f[i2 * N], f[size_t(H) * N * N + i2 * N]};
+    } else {
+      const double* f = static_cast<const double*>(a.f) + base;
+#pragma unroll
+      for (int i2 = 0; i2 < N; ++i2) z[i2] = {float(f[i2 * N]), float(f[size_t(H) * N * N + i2 * N])};
+    }
+    bzk::fft<N, -1>(z);
+#pragma unroll
+    for (int k2 = 0; k2 <= H; ++k2) {
+      const cx<float> zp = z[k2], zm = z[(N - k2) % N];
+      // transform of row i1: (Z(k) + conj Z(-k)) / 2; of row i1 + N/2: (Z(k) - conj Z(-k)) / 2i
+      lds[(k2 * N + i1) * P + i3] = cx<float>{0.5f * (zp.x + zm.x), 0.5f * (zp.y - zm.y)};
+      lds[(k2 * N + i1 + H) * P + i3] = cx<float>{0.5f * (zp.y + zm.y), 0.5f * (zm.x - zp.x)};
+    }
+  }
+  lds_barrier();
+  for (int q = t; q < (H + 1) * N; q += T) {
+    const int k2 = q / N, i3 = q % N;
+    cx<float> x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const int i1 = bzk::first_stage_order<N>(r);
+      x[i1] = lds[(k2 * N + i1) * P + i3];
+    }
+    bzk::fft<N, -1>(x);
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) lds[(k2 * N + k1) * P + i3] = x[k1];
+  }
+  lds_barrier();
+  const float scale = 1.0f / float(N * N * N);
+  cx<float>* fh = a.fh + cell * a.fh_stride;
+  for (int q = t; q < (H + 1) * N; q += T) {
+    const int k2 = q / N, k1 = q % N;
+    cx<float> x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const int i3 = bzk::first_stage_order<N>(r);
+      x[i3] = lds[(k2 * N + k1) * P + i3];
+    }
+    bzk::fft<N, -1>(x);
+#pragma unroll
+    for (int k3 = 0; k3 < N; ++k3)
+      fh[(size_t(k2) * N + k3) * N + k1] = cx<float>{x[k3].x * scale, x[k3].y * scale};
+    if (a.mirror && k2 > 0 && k2 < H) {
+      const int mk1 = (N - k1) % N;
+#pragma unroll
+      for (int k3 = 0; k3 < N; ++k3)
+        fh[(size_t(N - k2) * N + (N - k3) % N) * N + mk1] = cx<float>{x[k3].x * scale, -x[k3].y * scale};
+    }
+  }
+}
+
 // N^2/S threads; S j3-slices of width W = N/S.
 //   stage A: thread t owns pencils P = a*T + t (a < S) along k3 at
 //            (k1, k2) = (P % N, P / N);
@@ -670,6 +762,11 @@ bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStre
   return BZ_OK;
 }
 
+template <int N>
+void launch_fwd_fused(const FwdArgs& a, int ncells, hipStream_t s) {
+  hipLaunchKernelGGL((k_fwd_fused<N>), dim3(unsigned(ncells)), dim3(N * N / 2), 0, s, a);
+}
+
 template <int N, int S>
 void launch_fused(const FusedArgs& a, int ncells, hipStream_t s) {
   const dim3 grid(unsigned(ncells * a.chunks)), block(N * N / S);
@@ -731,8 +828,19 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
     a.mult = static_cast<const cx<float>*>(b.tables);
     a.w = reinterpret_cast<const float*>(static_cast<const char*>(b.tables) + p->table_w_off);
     if (p->transform == BZ_XF_FUSED) {
-      st = run_plain<float>(p, a, ncells, s, true, timed);
-      if (st != BZ_OK) return st;
+      FwdArgs fw{};
+      fw.ncells = ncells;
+      fw.ncells_dev = ncells_dev;
+      fw.f = f;
+      fw.f_fp32 = f_fp32;
+      fw.idx = idx;
+      fw.fh = a.fh;
+      fw.fh_stride = a.fh_stride;
+      fw.mirror = p->slices == 1 ? 1 : 0;  // the paired (two-slice) kernels read rows 0..N/2 only
+      if (p->n == 32) launch_fwd_fused<32>(fw, ncells, s);
+      else if (p->n == 16) launch_fwd_fused<16>(fw, ncells, s);
+      else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
+      if (timed) (void)hipEventRecord(pm->ev[1], s);
       FusedArgs fa{};
       fa.ncells = ncells;
       fa.ncells_dev = ncells_dev;

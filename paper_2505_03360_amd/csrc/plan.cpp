@@ -321,9 +321,12 @@ void layout(bz_plan* p) {
   p->table_mult_bytes = align256(size_t(p->m1) * n3 * 2 * es);
   p->table_w_off = p->table_mult_bytes;
   p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
-  const int acc_chunks = p->transform == BZ_XF_FUSED ? p->chunks : 1;
+  // fused: the forward transform keeps its intermediate volumes on chip (no y),
+  // and with one chunk and the projection on, the products never leave the chip (no acc)
+  const bool fused = p->transform == BZ_XF_FUSED;
+  const int acc_chunks = fused ? ((p->chunks == 1 && p->project) ? 0 : p->chunks) : 1;
   p->ws.fh_cell = align256(n3 * 2 * es);
-  p->ws.y_cell = align256(n3 * 2 * es);
+  p->ws.y_cell = fused ? 0 : align256(n3 * 2 * es);
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws_fixed = 0;
   p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell;
