@@ -14,6 +14,9 @@ Modules
               conservative moment projection.
   directions  hemisphere quadrature rules (icosahedral axes, the paper's
               (theta, phi) product grid, equal-weight golden spiral).
+  kinetic     macroscopic fields, the Maxwellian, the L1 distance of the
+              kinetic-to-fluid criterion, and the penalised first-order IMEX
+              update of the Boltzmann layer.
   mask        the realizability indicators of Sec. 3.2-3.3 / 4.5 and the
               regime update of Algorithm 1, in a fixed FP64 operation order.
 """

@@ -1,0 +1,147 @@
+"""Pins of the kinetic oracle (macroscopic fields, Maxwellian, L1 distance,
+penalised IMEX update) against closed forms and exact identities."""
+import math
+
+import numpy as np
+import pytest
+
+import bz_inputs as gen
+from oracle import directions, kinetic, spectral
+
+
+def grid(n, L):
+    return kinetic._grid(n, L)
+
+
+def test_moments_of_a_maxwellian():
+    # trapezoidal sums of a resolved Gaussian are exact to rounding
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(1.7, [0.4, -0.3, 0.25], 0.8, n, L)
+    rho, u, T = kinetic.moments(f, n, L)
+    assert abs(rho - 1.7) <= 1e-13 * 1.7
+    assert np.abs(u - [0.4, -0.3, 0.25]).max() <= 1e-13
+    assert abs(T - 0.8) <= 1e-12
+
+
+def test_moments_of_a_mixture():
+    # rho = sum rho_i, rho u = sum rho_i u_i, 3 rho T + rho |u|^2 = sum rho_i (3 T_i + |u_i|^2)
+    n, L = 48, 10.0
+    parts = [(0.9, np.array([1.2, 0.0, -0.5]), 0.6), (0.6, np.array([-0.8, 0.7, 0.3]), 1.4)]
+    f = sum(kinetic.maxwellian(r, u, T, n, L) for r, u, T in parts)
+    rho_x = sum(r for r, _, _ in parts)
+    u_x = sum(r * u for r, u, _ in parts) / rho_x
+    T_x = (sum(r * (3 * T + u @ u) for r, u, T in parts) - rho_x * u_x @ u_x) / (3 * rho_x)
+    rho, u, T = kinetic.moments(f, n, L)
+    assert abs(rho - rho_x) <= 1e-13
+    assert np.abs(u - u_x).max() <= 1e-13
+    assert abs(T - T_x) <= 1e-12
+
+
+def test_l1_of_a_maxwellian_vanishes():
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(1.1, [0.3, 0.1, -0.2], 1.2, n, L)
+    assert kinetic.l1_distance(f, n, L) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["normal_stress", "shear_stress"])
+def test_l1_closed_form(kind):
+    # f = M (1 + a h) with h orthogonal to 1, v, |v|^2 under M keeps M[f] = M, so
+    # ||f - M||_1 = rho |a| E|h|:  E|X^2 - Y^2| = 4T/pi,  E|XY| = 2T/pi  (X, Y ~ N(0, T))
+    n, L, rho, u, T, a = 64, 8.0, 1.3, np.array([0.2, -0.1, 0.3]), 1.0, 0.1
+    V1, V2, V3, _ = grid(n, L)
+    M = kinetic.maxwellian(rho, u, T, n, L)
+    if kind == "normal_stress":
+        h, mean_abs = ((V1 - u[0]) ** 2 - (V2 - u[1]) ** 2) / T, 4.0 / math.pi
+    else:
+        h, mean_abs = (V1 - u[0]) * (V2 - u[1]) / T, 2.0 / math.pi
+    f = M * (1.0 + a * h)
+    r2, u2, T2 = kinetic.moments(f, n, L)
+    assert abs(r2 - rho) <= 1e-12 and np.abs(u2 - u).max() <= 1e-12 and abs(T2 - T) <= 1e-10
+    # the integrand has kinks on the planes where h changes sign: O(dv^2) quadrature error
+    assert abs(kinetic.l1_distance(f, n, L) / (rho * a * mean_abs) - 1.0) <= 5e-3
+
+
+def test_conserved_and_maxwellian_of_conserved():
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(0.7, [0.5, -0.2, 0.1], 0.9, n, L)
+    U = kinetic.conserved(f, n, L)
+    assert np.allclose(U, [0.7, 0.35, -0.14, 0.07, 0.7 * (3 * 0.9 + 0.25 + 0.04 + 0.01)], rtol=0, atol=1e-13)
+    M, rho = kinetic.maxwellian_of_conserved(U, n, L)
+    assert abs(rho - 0.7) <= 1e-14
+    assert np.abs(M - f).max() <= 1e-13 * f.max()
+
+
+def random_transport(n, L, seed):
+    # a smooth, seeded stand-in for v . grad_x f (any array works for the identities below)
+    rng = np.random.default_rng(seed)
+    V1, V2, V3, _ = grid(n, L)
+    c = rng.uniform(-1, 1, 3)
+    return (c[0] * V1 + c[1] * V2 + c[2] * V3) * kinetic.maxwellian(1.0, rng.uniform(-0.5, 0.5, 3), 1.0, n, L)
+
+
+def test_imex_homogeneous_closed_form():
+    # tr = 0: U^{n+1} = U^n, M^{n+1} = M^n, so f^{n+1} = f + dt Q / (eps + 2 pi rho dt)
+    n, L = 32, 8.0
+    f = gen.shock_batch(1, n, L, seed=11)[0]
+    q = np.random.default_rng(3).standard_normal(f.shape) * 1e-3
+    dt, eps = 0.01, 0.05
+    rho = kinetic.moments(f, n, L)[0]
+    out = kinetic.imex_combine(f, np.zeros_like(f), q, dt, eps, L)
+    want = f + dt * q / (eps + 2 * math.pi * rho * dt)
+    assert np.abs(out - want).max() <= 1e-13 * np.abs(f).max()
+
+
+def test_imex_limits():
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(1.0, [0.2, 0.0, -0.1], 1.0, n, L)
+    tr = random_transport(n, L, 5)
+    dt = 0.02
+    g = f - dt * tr
+    # eps >> beta dt: free transport
+    out = kinetic.imex_combine(f, tr, np.zeros_like(f), dt, 1e12, L)
+    assert np.abs(out - g).max() <= 1e-10 * np.abs(g).max()
+    # eps -> 0 from equilibrium: the Maxwellian of U^{n+1} (asymptotic preservation)
+    out = kinetic.imex_combine(f, tr, np.zeros_like(f), dt, 1e-14, L)
+    M1, _ = kinetic.maxwellian_of_conserved(kinetic.conserved(g, n, L), n, L)
+    assert np.abs(out - M1).max() <= 1e-11 * M1.max()
+
+
+def test_imex_conserves_the_transported_moments():
+    # with Q free of the invariants: int phi f^{n+1} = U^{n+1} = int phi (f - dt tr)
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(0.8, [0.3, -0.2, 0.0], 0.7, n, L) + kinetic.maxwellian(0.4, [-0.6, 0.4, 0.2], 1.3, n, L)
+    tr = random_transport(n, L, 6)
+    q = spectral.project(np.random.default_rng(7).standard_normal(f.shape) * 1e-2, n, L)
+    dt, eps = 0.01, 0.02
+    out = kinetic.imex_combine(f, tr, q, dt, eps, L)
+    U1 = kinetic.conserved(f - dt * tr, n, L)
+    assert np.abs(kinetic.conserved(out, n, L) - U1).max() <= 1e-12 * np.abs(U1).max()
+
+
+def test_imex_euler_uses_the_projected_operator():
+    n, L = 16, 8.0
+    d, w = directions.icosa6()
+    plan = spectral.Plan(n, L, spectral.default_R(L), 1.0, 4.0, d, w)
+    f = gen.bimaxwellian_batch(1, n, L, seed=1)[0]
+    dt, eps = 0.005, 0.1
+    out = kinetic.imex_euler(f, np.zeros_like(f), dt, eps, plan)
+    q = spectral.project(spectral.collide(f, plan), n, L)
+    rho = kinetic.moments(f, n, L)[0]
+    assert np.abs(out - (f + dt * q / (eps + 2 * math.pi * rho * dt))).max() <= 1e-13 * np.abs(f).max()
+
+
+def test_imex_penalty_uses_the_new_density():
+    # from equilibrium with q = 0: f^{n+1} = (eps g + beta dt M^{n+1}) / (eps + beta dt),
+    # beta = 2 pi rho^{n+1} with rho^{n+1} the density of g = f - dt tr (transport changes it)
+    n, L = 48, 10.0
+    f = kinetic.maxwellian(1.0, [0.1, 0.2, 0.0], 0.9, n, L)
+    V1, V2, V3, _ = grid(n, L)
+    tr = 3.0 * f * (1.0 + 0.2 * V1)  # carries mass: rho(g) = (1 - 3 dt) rho(f) - ...
+    dt, eps = 0.02, 0.03
+    g = f - dt * tr
+    M1, rho1 = kinetic.maxwellian_of_conserved(kinetic.conserved(g, n, L), n, L)
+    assert abs(rho1 - 1.0) > 0.05
+    beta = 2 * math.pi * rho1
+    want = (eps * g + beta * dt * M1) / (eps + beta * dt)
+    out = kinetic.imex_combine(f, tr, np.zeros_like(f), dt, eps, L)
+    assert np.abs(out - want).max() <= 1e-12 * np.abs(want).max()
