@@ -31,7 +31,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM-side bytes per launch of k_collide_fused<32,2> on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain
 # 256 MiB copy needs); set to None whenever the kernel changes until re-measured.
-FUSED_TRAFFIC_BYTES = (228872 * 2.0 + 124019 * 1.0) * 1024
+FUSED_TRAFFIC_BYTES = (261861 * 2.0 + 124429 * 1.0) * 1024
 
 
 def algorithmic_flops(n: int, m: int):
@@ -212,6 +212,39 @@ def sweep(cells: int = 1024, reps: int = 3):
     return out
 
 
+def kinetic_run(col, f, steps: int):
+    """The per-cell kinetic steps on the same batch: macroscopic fields + L1
+    distance (bz_cell_moments) and one penalised IMEX step (bz_imex_euler,
+    eq. 1002) fused with the collision evaluation.  Times from HIP events on
+    the current stream."""
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    mom = bz.cell_moments(f, L)
+    ev[0].record()
+    for _ in range(steps):
+        bz.cell_moments(f, L, out=mom)
+    ev[1].record()
+    tr = f * torch.from_numpy(gen.velocity_axis(N, L)).cuda().view(1, N, 1, 1)  # v1 f as a transport stand-in
+    fo = torch.empty_like(f)
+    col.imex_euler(f, tr, 0.01, eps=0.01, out=fo)
+    ev[2].record()
+    for _ in range(steps):
+        col.imex_euler(f, tr, 0.01, eps=0.01, out=fo)
+    ev[3].record()
+    torch.cuda.synchronize()
+    mom_ms = ev[0].elapsed_time(ev[1]) / steps
+    imex_ms = ev[2].elapsed_time(ev[3]) / steps
+    cells = f.shape[0]
+    return {"moments_l1_ms": mom_ms,
+            "moments_l1_compulsory_GB_s": cells * 8 * N ** 3 / (mom_ms * 1e-3) / 1e9,
+            "imex_euler_ms": imex_ms, "imex_euler_cells_per_s": cells / (imex_ms * 1e-3),
+            "workload": f"{cells} cells N=32 M=32 FP32 collision + FP64 IMEX (eq. 1002), dt=0.01, eps=0.01"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +350,7 @@ def main():
                                 "max_cell_unfloored": float(diff.max())},
         "algorithmic_tflops_whole_step": total_flops * value / 1e12,
     }
+    rec["kinetic"] = kinetic_run(col, f, max(2, args.steps // 2))
     if args.serve_seconds > 0:
         del out64, col64
         torch.cuda.empty_cache()

@@ -197,6 +197,58 @@ bz_status bz_collide_batch(const bz_plan* plan, const void* f, int32_t f_dtype,
 bz_status bz_plan_set_timing(bz_plan* plan, int32_t enable);
 bz_status bz_plan_last_times(bz_plan* plan, float* ms, int32_t n);
 
+/*
+ * Macroscopic fields of a batch of cells (Sec. 2: the density, velocity and
+ * temperature that define the equilibria (H3)) and the L1 distance of the
+ * kinetic-to-fluid criterion (Sec. 3.3), in FP64 over the velocity grid:
+ *   rho = dv^3 sum_j f_j,  u = sum_j v_j f_j / sum_j f_j,
+ *   T = (sum_j |v_j|^2 f_j / sum_j f_j - |u|^2) / 3,
+ *   l1 = dv^3 sum_j |f_j - rho (2 pi T)^(-3/2) exp(-|v_j - u|^2 / (2T))|.
+ * n: 16, 24, 32 or 48 (BZ_ERR_UNSUPPORTED otherwise); L > 0.
+ * f, idx, ncells, ncells_dev: as for bz_collide_batch.
+ * out: host struct of device FP64 arrays, each NULL (not computed / not
+ *      written) or written at position c (compact) or idx[c] (BZ_SCATTER), so
+ *      that rho, u1 (-> ux), u2 (-> uy), T and l1 can be written straight into
+ *      the [ny][nx] inputs of bz_realizability_mask.  Cells with sum f <= 0
+ *      give non-finite u, T and l1 (the mask then counts them as invalid).
+ * Asynchronous on `stream`; per-cell results do not depend on the batch.
+ */
+typedef struct {
+  double *rho, *u1, *u2, *u3, *T, *l1;
+} bz_moments_out;
+
+bz_status bz_cell_moments(int32_t n, double L, const void* f, int32_t f_dtype, const int32_t* idx,
+                          int32_t ncells, const int32_t* ncells_dev, const bz_moments_out* out,
+                          int32_t flags, void* stream);
+
+/*
+ * One step of the penalised first-order IMEX scheme of the Boltzmann layer
+ * (Sec. 4.4, eq. 1002, after Filbet and Jin), fused with the evaluation of
+ * Q(f^n) by `plan`:
+ *   g = f^n - dt tr,  U^{n+1} = int (1, v, |v|^2) g  (Q and P conserve them),
+ *   beta = 2 pi rho^{n+1},  P(h) = beta (M[h] - h),
+ *   f^{n+1} = (eps g + dt (Q(f^n) - P(f^n)) + beta dt M^{n+1}) / (eps + beta dt),
+ * M^n the Maxwellian of f^n's moments, M^{n+1} that of U^{n+1}; Q is the
+ * plan's operator (FP64 projected when the plan projects).
+ * desc:   dt > 0; eps > 0 used when eps_cells is NULL, else eps_cells (device
+ *         FP64, read at the rows of f) holds the Knudsen number per row.
+ * f, tr:  device FP64 [*][n][n][n]: f^n and the transport term v . grad_x f^n,
+ *         cell c at row idx[c] (idx NULL: row c).
+ * f_out:  device FP64, row c or idx[c] (BZ_SCATTER); may equal f when the
+ *         rows written are the rows read (BZ_SCATTER, or no idx).
+ * ncells <= the plan's capacity; ncells_dev as for bz_collide_batch.
+ * The plan must be bound; asynchronous on `stream`.
+ */
+typedef struct {
+  double dt;
+  double eps;
+  const double* eps_cells;
+} bz_imex_desc;
+
+bz_status bz_imex_euler(const bz_plan* plan, const bz_imex_desc* desc, const double* f, const double* tr,
+                        const int32_t* idx, int32_t ncells, const int32_t* ncells_dev, double* f_out,
+                        int32_t flags, void* stream);
+
 /* Mask descriptor (Sec. 3.3, 4.5, Algorithm 1). */
 typedef struct {
   int32_t nx, ny;           /* spatial grid, arrays are row-major [iy][ix] */

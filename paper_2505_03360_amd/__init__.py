@@ -94,6 +94,14 @@ class BzStepBuffers(ctypes.Structure):
                 ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32), ("q", ctypes.c_void_p)]
 
 
+class BzMomentsOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("rho", "u1", "u2", "u3", "T", "l1")]
+
+
+class BzImexDesc(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("eps", ctypes.c_double), ("eps_cells", ctypes.c_void_p)]
+
+
 class BzError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"bz error {code}: {msg}")
@@ -121,6 +129,9 @@ SIGNATURES = [
     ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
     ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_plan_set_timing", _I32, [_VP, _I32]),
+    ("bz_cell_moments", _I32, [_I32, ctypes.c_double, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(BzMomentsOut),
+                               _I32, _VP]),
+    ("bz_imex_euler", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_plan_last_times", _I32, [_VP, ctypes.POINTER(ctypes.c_float), _I32]),
     ("bz_realizability_mask", _I32, [ctypes.POINTER(BzMaskDesc), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -251,6 +262,16 @@ def bz_collide_batch(plan: int, f: int, f_dtype: int, idx: int, ncells: int, nce
     _check(lib().bz_collide_batch(plan, f, f_dtype, idx, ncells, ncells_dev, q, flags, stream))
 
 
+def bz_cell_moments(n: int, L: float, f: int, f_dtype: int, idx: int, ncells: int, ncells_dev: int,
+                    out: BzMomentsOut, flags: int = 0, stream: int = 0) -> None:
+    _check(lib().bz_cell_moments(n, L, f, f_dtype, idx, ncells, ncells_dev, ctypes.byref(out), flags, stream))
+
+
+def bz_imex_euler(plan: int, desc: BzImexDesc, f: int, tr: int, idx: int, ncells: int, ncells_dev: int,
+                  f_out: int, flags: int = 0, stream: int = 0) -> None:
+    _check(lib().bz_imex_euler(plan, ctypes.byref(desc), f, tr, idx, ncells, ncells_dev, f_out, flags, stream))
+
+
 def bz_plan_set_timing(plan: int, enable: bool) -> None:
     _check(lib().bz_plan_set_timing(plan, 1 if enable else 0))
 
@@ -361,6 +382,22 @@ class Collider:
                          BZ_SCATTER if scatter else 0, _stream(stream))
         return out
 
+    def imex_euler(self, f, tr, dt: float, eps: float = 0.0, eps_cells=None, idx=None, ncells=None,
+                   ncells_dev=None, out=None, scatter=False, stream=None):
+        """One penalised IMEX step (bz_imex_euler) on FP64 CUDA tensors."""
+        torch = _torch()
+        for t in (f, tr):
+            if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("f and tr must be contiguous CUDA float64 tensors")
+        if ncells is None:
+            ncells = idx.numel() if idx is not None else f.numel() // self.n ** 3
+        if out is None:
+            out = torch.empty((ncells, self.n, self.n, self.n), dtype=torch.float64, device=f.device)
+        d = BzImexDesc(dt, eps, _ptr(eps_cells))
+        bz_imex_euler(self.plan, d, _ptr(f), _ptr(tr), _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
+                      BZ_SCATTER if scatter else 0, _stream(stream))
+        return out
+
     def close(self):
         if self.plan:
             bz_plan_destroy(self.plan)
@@ -371,6 +408,25 @@ class Collider:
             self.close()
         except Exception:
             pass
+
+
+def cell_moments(f, L: float, idx=None, ncells=None, ncells_dev=None, out=None, scatter=False,
+                 l1=True, stream=None):
+    """bz_cell_moments on a CUDA tensor [*][n][n][n]; returns a dict of FP64
+    tensors rho, u1, u2, u3, T (and l1) indexed like the output rows."""
+    torch = _torch()
+    n = f.shape[-1]
+    if ncells is None:
+        ncells = idx.numel() if idx is not None else f.numel() // n ** 3
+    if out is None:
+        rows = f.numel() // n ** 3 if scatter else ncells
+        keys = ("rho", "u1", "u2", "u3", "T") + (("l1",) if l1 else ())
+        out = {k: torch.zeros(rows, dtype=torch.float64, device=f.device) for k in keys}
+    o = BzMomentsOut(*[_ptr(out.get(k)) for k in ("rho", "u1", "u2", "u3", "T", "l1")])
+    fd = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
+    bz_cell_moments(n, L, _ptr(f), fd, _ptr(idx), ncells, _ptr(ncells_dev), o,
+                    BZ_SCATTER if scatter else 0, _stream(stream))
+    return out
 
 
 class Server:

@@ -21,6 +21,7 @@ LIB = os.path.join(PKG, "libbz.so")
 SOURCES = [
     ("collide.hip", []),
     ("mask.hip", ["-ffp-contract=off"]),
+    ("kinetic.hip", []),
     ("plan.cpp", []),
     ("server.cpp", []),
     ("step.cpp", []),

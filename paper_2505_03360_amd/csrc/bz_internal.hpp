@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "bz.h"
+#include "kinetic.hpp"
 
 namespace bz {
 
@@ -20,8 +21,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace regions of a bound plan, each [capacity][...].
 struct WsLayout {
-  size_t fh_off, y_off, acc_off;  // byte offsets into ws_dev
-  size_t fh_cell, y_cell, acc_cell;  // bytes per cell of each region
+  size_t fh_off, y_off, acc_off, par_off;  // byte offsets into ws_dev
+  size_t fh_cell, y_cell, acc_cell, par_cell;  // bytes per cell of each region
 };
 
 // Device memory one evaluation runs on: the plan's uploaded tables and a
@@ -75,7 +76,11 @@ namespace bz {
 // kernel launchers (collide.hip); `timed` records the plan's timing events
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
-                         int scatter, hipStream_t s, bool timed);
+                         int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex = nullptr);
+// per-cell IMEX parameters (kinetic.hip)
+bool kinetic_n_supported(int n);
+bz_status launch_imex_params(int n, double dv, const int32_t* idx, int ncells, const int32_t* ncells_dev,
+                             const double* f, const double* tr, double dt, double* par, hipStream_t s);
 // plan helpers (plan.cpp)
 Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);

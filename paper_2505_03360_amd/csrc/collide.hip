@@ -28,6 +28,7 @@
 //          registers, and the products accumulated in registers (FP32).
 #include "bz_internal.hpp"
 #include "fft.hpp"
+#include "kinetic.hpp"
 
 using bzk::cx;
 
@@ -250,6 +251,9 @@ struct FusedArgs {
   double C, dv;
   double ginv[25];
   double* q;
+  int imex;           // write the IMEX update of eq. 1002 instead of Q (projection epilogue only;
+                      // selects the IMEX instantiation of the kernel)
+  bzk::ImexDev im;
 };
 
 // ------------------------------------------------------------------ fused forward
@@ -533,7 +537,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 template <int N, int S>
 constexpr int fused_min_waves() { return (N <= 16 && S == 1) ? 4 : 2; }
 
-template <int N, int S>
+template <int N, int S, bool IMEX>
 __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collide_fused(FusedArgs a) {
   constexpr int W = N / S;
   constexpr int AB = W + 1;
@@ -605,6 +609,7 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
     }
     const long orow = a.scatter ? row : long(cell);
     double* q = a.q + size_t(orow) * N * N * N;
+    [[maybe_unused]] const double eps_c = IMEX ? (a.im.eps_cells ? a.im.eps_cells[row] : a.im.eps) : 0.0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const double v3 = (s * W + tl - N / 2) * a.dv;
@@ -612,7 +617,15 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
       for (int j1 = 0; j1 < N; ++j1) {
         const double v1 = (j1 - N / 2) * a.dv;
         const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
-        q[size_t(j1) * N * N + size_t(j2) * N + s * W + tl] = a.C * double(acc[s][j1]) - corr;
+        const size_t e = size_t(j1) * N * N + size_t(j2) * N + s * W + tl;
+        const double qv = a.C * double(acc[s][j1]) - corr;
+        if constexpr (IMEX) {
+          const size_t fe = size_t(row) * N * N * N + e;
+          q[e] = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c,
+                                 a.im.dt, v1, v2, v3);
+        } else {
+          q[e] = qv;
+        }
       }
     }
     return;
@@ -640,6 +653,8 @@ struct ProjArgs {
   int project;  // 1: FP64 projection, FP64 output
   void* q;
   int q_fp32;   // output type when project == 0
+  int imex;     // write the IMEX update of eq. 1002 (FP64) instead of Q
+  bzk::ImexDev im;
 };
 
 __device__ __forceinline__ double load_acc(const ProjArgs& a, size_t i) {
@@ -656,12 +671,25 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   const size_t n3 = size_t(n) * n * n;
   const size_t base = size_t(c) * a.acc_stride;
   const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
+  const size_t frow = a.idx ? size_t(a.idx[c]) : size_t(c);  // row of the input f
   const int t = threadIdx.x;
   auto qraw = [&](size_t j) {
     double s = 0.0;
     for (int ch = 0; ch < a.chunks; ++ch) s += load_acc(a, base + size_t(ch) * n3 + j);
     return a.C * s;
   };
+  const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
+  auto imex_out = [&](size_t j, double qv) {
+    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
+    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
+    const size_t fe = frow * n3 + j;
+    return bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
+                           v1, v2, v3);
+  };
+  if (!a.project && a.imex) {
+    for (size_t j = t; j < n3; j += blockDim.x) static_cast<double*>(a.q)[row * n3 + j] = imex_out(j, qraw(j));
+    return;
+  }
   if (!a.project) {
     for (size_t j = t; j < n3; j += blockDim.x) {
       const double v = qraw(j);
@@ -704,7 +732,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
     const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
     const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
-    q[j] = qraw(j) - corr;
+    q[j] = a.imex ? imex_out(j, qraw(j) - corr) : qraw(j) - corr;
   }
 }
 
@@ -770,7 +798,8 @@ void launch_fwd_fused(const FwdArgs& a, int ncells, hipStream_t s) {
 template <int N, int S>
 void launch_fused(const FusedArgs& a, int ncells, hipStream_t s) {
   const dim3 grid(unsigned(ncells * a.chunks)), block(N * N / S);
-  hipLaunchKernelGGL((k_collide_fused<N, S>), grid, block, 0, s, a);
+  if (a.imex) hipLaunchKernelGGL((k_collide_fused<N, S, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_collide_fused<N, S, false>), grid, block, 0, s, a);
 }
 
 }  // namespace
@@ -785,7 +814,7 @@ int fused_default_chunks(int n) { return 1; }
 
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
-                         int scatter, hipStream_t s, bool timed) {
+                         int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex) {
   bz_plan* pm = const_cast<bz_plan*>(p);
   char* ws = static_cast<char*>(b.ws);
   const WsLayout& lay = b.lay;
@@ -810,6 +839,10 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   pa.project = p->project;
   pa.q = q;
   pa.q_fp32 = p->fp32;
+  if (imex) {
+    pa.imex = 1;
+    pa.im = *imex;
+  }
   bz_status st = BZ_OK;
   bool fused_projection = false;
   if (p->fp32) {
@@ -861,6 +894,10 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fa.dv = p->dv;
       for (int i = 0; i < 25; ++i) fa.ginv[i] = p->ginv[i];
       fa.q = static_cast<double*>(q);
+      if (imex && fa.fuse_project) {
+        fa.imex = 1;
+        fa.im = *imex;
+      }
       fused_projection = fa.fuse_project != 0;
       if (p->n == 32) launch_fused<32, 2>(fa, ncells, s);
       else if (p->n == 16 && p->slices == 1) launch_fused<16, 1>(fa, ncells, s);

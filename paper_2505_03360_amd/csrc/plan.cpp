@@ -328,8 +328,9 @@ void layout(bz_plan* p) {
   p->ws.fh_cell = align256(n3 * 2 * es);
   p->ws.y_cell = fused ? 0 : align256(n3 * 2 * es);
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
+  p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
   p->ws_fixed = 0;
-  p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell;
+  p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell + p->ws.par_cell;
 }
 
 
@@ -345,6 +346,7 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
   b.lay.fh_off = p->ws_fixed;
   b.lay.y_off = b.lay.fh_off + size_t(b.capacity) * b.lay.fh_cell;
   b.lay.acc_off = b.lay.y_off + size_t(b.capacity) * b.lay.y_cell;
+  b.lay.par_off = b.lay.acc_off + size_t(b.capacity) * b.lay.acc_cell;
   return b;
 }
 
@@ -625,6 +627,38 @@ bz_status bz_collide_batch(const bz_plan* p, const void* f, int32_t f_dtype, con
   b.lay = p->ws;
   return launch_collide(p, b, f, f_dtype == BZ_FP32, idx, ncells, ncells_dev, q,
                         (flags & BZ_SCATTER) != 0, static_cast<hipStream_t>(stream), p->timing);
+}
+
+bz_status bz_imex_euler(const bz_plan* p, const bz_imex_desc* d, const double* f, const double* tr,
+                        const int32_t* idx, int32_t ncells, const int32_t* ncells_dev, double* f_out,
+                        int32_t flags, void* stream) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_imex_euler: null plan");
+  if (!d) return fail(BZ_ERR_ARG, "bz_imex_euler: null descriptor");
+  if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_imex_euler: plan not bound");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(BZ_ERR_ARG, "bz_imex_euler: dt must be > 0");
+  if (!d->eps_cells && !(d->eps > 0.0)) return fail(BZ_ERR_ARG, "bz_imex_euler: eps must be > 0");
+  if (ncells < 0) return fail(BZ_ERR_ARG, "bz_imex_euler: ncells < 0");
+  if (flags & ~int32_t(BZ_SCATTER)) return fail(BZ_ERR_ARG, "bz_imex_euler: unknown flags");
+  if ((flags & BZ_SCATTER) && !idx) return fail(BZ_ERR_ARG, "bz_imex_euler: BZ_SCATTER needs idx");
+  if (ncells == 0) return BZ_OK;
+  if (!f || !tr || !f_out) return fail(BZ_ERR_ARG, "bz_imex_euler: null f, tr or f_out");
+  if (f_out == f && idx && !(flags & BZ_SCATTER))
+    return fail(BZ_ERR_ARG, "bz_imex_euler: in place with idx needs BZ_SCATTER");
+  if (!p->project && p->fp32) return fail(BZ_ERR_UNSUPPORTED, "bz_imex_euler: an FP32 plan must project (FP64 output)");
+  if (ncells > p->capacity)
+    return fail(BZ_ERR_NOMEM, "bz_imex_euler: %d cells exceed the bound capacity %d", ncells, p->capacity);
+  Binding b;
+  b.tables = p->tables_dev;
+  b.ws = p->ws_dev;
+  b.capacity = p->capacity;
+  b.lay = p->ws;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* par = reinterpret_cast<double*>(static_cast<char*>(b.ws) + b.lay.par_off);
+  bz_status st = launch_imex_params(p->n, p->dv, idx, ncells, ncells_dev, f, tr, d->dt, par, s);
+  if (st != BZ_OK) return st;
+  bzk::ImexDev im{par, f, tr, d->eps_cells, d->eps, d->dt};
+  return launch_collide(p, b, f, 0, idx, ncells, ncells_dev, f_out, (flags & BZ_SCATTER) != 0, s, p->timing, &im);
 }
 
 }  // extern "C"

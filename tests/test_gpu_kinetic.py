@@ -1,0 +1,140 @@
+"""Cell moments / L1 distance and the penalised IMEX step on the GPU against
+the oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import bz_inputs as gen
+from oracle import kinetic, spectral
+from tests.gpu_util import lib_kwargs, oracle_cells, oracle_plan
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 48])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_moments_against_oracle(n, dtype):
+    import paper_2505_03360_amd as bz
+    print("case moments", n, dtype, flush=True)
+    L = 8.0
+    f = gen.shock_batch(7, n, L, seed=n)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)  # the values the GPU reads
+    ft = torch.from_numpy(f.astype(np.float32) if dtype == "f32" else f).cuda()
+    idx = torch.tensor([5, 0, 3, 6], dtype=torch.int32, device="cuda")
+    got = bz.cell_moments(ft, L, idx=idx, scatter=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    for r in range(7):
+        if r not in (5, 0, 3, 6):
+            assert all(got[k][r] == 0.0 for k in got)  # rows not listed are not written
+            continue
+        rho, u, T = kinetic.moments(f[r], n, L)
+        l1 = kinetic.l1_distance(f[r], n, L)
+        assert abs(got["rho"][r] - rho) <= 1e-13 * rho
+        assert max(abs(got["u1"][r] - u[0]), abs(got["u2"][r] - u[1]), abs(got["u3"][r] - u[2])) <= 1e-12
+        assert abs(got["T"][r] - T) <= 1e-12 * T
+        assert abs(got["l1"][r] - l1) <= 1e-12 * rho
+    # compact output, no idx, l1 off
+    got = bz.cell_moments(ft, L, l1=False)
+    torch.cuda.synchronize()
+    rho0 = kinetic.moments(f[0], n, L)[0]
+    assert abs(float(got["rho"][0]) - rho0) <= 1e-13 * rho0 and "l1" not in got
+
+
+def transport(f, n, L, seed):
+    # seeded stand-in for v . grad_x f: a velocity-weighted smooth perturbation of f
+    rng = np.random.default_rng(seed)
+    v = spectral.velocity_nodes(n, L)
+    V1, V2, V3 = np.meshgrid(v, v, v, indexing="ij")
+    out = np.empty_like(f)
+    for c in range(f.shape[0]):
+        k = rng.uniform(-0.5, 0.5, 3)
+        out[c] = (k[0] * V1 + k[1] * V2 + k[2] * V3) * f[c] * rng.uniform(0.5, 2.0)
+    return out
+
+
+CASES = [
+    # (n, rule, m, precision, slices)
+    (16, "icosa6", 6, "fp64", 0),
+    (16, "icosa6", 6, "fp32", 1),
+    (16, "spiral", 32, "fp32", 2),
+    (24, "spiral", 32, "fp32", 0),
+    (32, "spiral", 32, "fp32", 2),
+    (32, "spiral", 32, "fp64", 0),
+]
+
+
+@pytest.mark.parametrize("n,rule,m,prec,slices", CASES)
+def test_imex_euler_against_oracle(n, rule, m, prec, slices):
+    import paper_2505_03360_amd as bz
+    print("case imex", n, rule, m, prec, slices, flush=True)
+    L, dt = 8.0, 0.01
+    cells = 3
+    f = gen.shock_batch(5, n, L, seed=21 + n)
+    tr = transport(f, n, L, 9)
+    eps_rows = np.array([0.01, 1.0, 0.003, 0.05, 1e-4])
+    rows = [4, 1, 2]
+    plan = oracle_plan(n, rule=rule, m=m)
+    sel = f[rows]
+    q_ref, loss_ref = oracle_cells(sel, plan)
+    ref = np.stack([kinetic.imex_combine(sel[c], tr[rows[c]], q_ref[c], dt, eps_rows[rows[c]], L)
+                    for c in range(cells)])
+    kw = lib_kwargs(rule, m)
+    col = bz.Collider(n, cells, L=L, precision=bz.BZ_FP32 if prec == "fp32" else bz.BZ_FP64, slices=slices, **kw)
+    ft, trt = torch.from_numpy(f).cuda(), torch.from_numpy(tr).cuda()
+    idx = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    et = torch.from_numpy(eps_rows).cuda()
+    out = col.imex_euler(ft, trt, dt, eps_cells=et, idx=idx)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    tol_q = 1e-5 if prec == "fp32" else 1e-12
+    for c in range(cells):
+        rho1 = kinetic.conserved(sel[c] - dt * tr[rows[c]], n, L)[0]
+        sens = dt / (eps_rows[rows[c]] + 2 * math.pi * rho1 * dt)  # d f^{n+1} / d Q
+        qn = max(np.linalg.norm(q_ref[c]), 0.05 * np.linalg.norm(loss_ref[c]))
+        err = np.linalg.norm(out[c] - ref[c])
+        bound = tol_q * sens * qn + 1e-13 * np.linalg.norm(ref[c])
+        print(f"  cell {c}: err {err:.3e} bound {bound:.3e}", flush=True)
+        assert err <= bound
+    # scalar eps, in place over the listed rows (scatter), against the same oracle
+    ref2 = [kinetic.imex_combine(sel[c], tr[rows[c]], q_ref[c], dt, 0.02, L) for c in range(cells)]
+    col.imex_euler(ft, trt, dt, eps=0.02, idx=idx, out=ft, scatter=True)
+    torch.cuda.synchronize()
+    got = ft.cpu().numpy()
+    for c in range(cells):
+        rho1 = kinetic.conserved(sel[c] - dt * tr[rows[c]], n, L)[0]
+        sens = dt / (0.02 + 2 * math.pi * rho1 * dt)
+        qn = max(np.linalg.norm(q_ref[c]), 0.05 * np.linalg.norm(loss_ref[c]))
+        assert np.linalg.norm(got[rows[c]] - ref2[c]) <= tol_q * sens * qn + 1e-13 * np.linalg.norm(ref2[c])
+    assert np.array_equal(got[[0, 3]], f[[0, 3]])  # rows not listed untouched
+    col.close()
+
+
+def test_imex_equilibrium_and_conservation():
+    # f^n Maxwellian, no transport: f^{n+1} = f^n + dt Q(M)/(eps + beta dt) stays Maxwellian;
+    # with transport the invariants of f^{n+1} are those of f^n - dt tr
+    import paper_2505_03360_amd as bz
+    print("case imex equilibrium", flush=True)
+    n, L = 32, 8.0
+    v = spectral.velocity_nodes(n, L)
+    M = kinetic.maxwellian(1.0, [0.3, -0.2, 0.1], 1.0, n, L)[None]
+    f = np.concatenate([M, gen.shock_batch(1, n, L, seed=3)])
+    tr = transport(f, n, L, 4)
+    col = bz.Collider(n, 2, L=L, precision=bz.BZ_FP32, m=32, dir_kind=bz.BZ_DIRS_SPIRAL)
+    ft = torch.from_numpy(f).cuda()
+    out = col.imex_euler(ft, torch.zeros_like(ft), 0.01, eps=1e-3).cpu().numpy()
+    assert np.abs(out[0] - M[0]).max() <= 1e-6 * M.max()
+    out = col.imex_euler(ft, torch.from_numpy(tr).cuda(), 0.01, eps=1e-3).cpu().numpy()
+    for c in range(2):
+        U1 = kinetic.conserved(f[c] - 0.01 * tr[c], n, L)
+        assert np.abs(kinetic.conserved(out[c], n, L) - U1).max() <= 1e-6 * np.abs(U1).max()
+    col.close()

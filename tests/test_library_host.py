@@ -106,3 +106,22 @@ def test_device_bytes_scale():
     assert bz.bz_plan_transform(p) == bz.BZ_XF_PLAIN
     assert bz.bz_plan_device_bytes(p)[2] >= 32 ** 3 * (16 + 16 + 8)  # fhat, scratch volume, accumulator
     bz.bz_plan_destroy(p)
+
+
+def test_moments_and_imex_validation():
+    out = bz.BzMomentsOut()
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_cell_moments(20, 8.0, 0, bz.BZ_FP64, 0, 4, 0, out)
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_cell_moments(32, 0.0, 0, bz.BZ_FP64, 0, 4, 0, out)
+    assert e.value.code == bz.BZ_ERR_ARG
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_cell_moments(32, 8.0, 0, bz.BZ_FP64, 0, 4, 0, out, flags=bz.BZ_SCATTER)
+    assert e.value.code == bz.BZ_ERR_ARG
+    bz.bz_cell_moments(32, 8.0, 0, bz.BZ_FP64, 0, 0, 0, out)  # empty batch: nothing to do
+    p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=6, precision=bz.BZ_FP64))
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_imex_euler(p, bz.BzImexDesc(0.01, 0.1, None), 0, 0, 0, 1, 0, 0)
+    assert e.value.code == bz.BZ_ERR_STATE  # not bound
+    bz.bz_plan_destroy(p)
