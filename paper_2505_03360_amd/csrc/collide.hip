@@ -352,18 +352,23 @@ __global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
 //   stage A: thread t owns pencils P = a*T + t (a < S) along k3 at
 //            (k1, k2) = (P % N, P / N);
 //   stage B: thread t owns, in every slice, the pencil along k2 at
-//            (k1, j3) = (t / W, s*W + t % W);
+//            (k1, j3) = (t % N, s*W + t / N);
 //   stage C: thread t owns, in every slice, the pencil along k1 at
 //            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
-// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
-// lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
+// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride: the stage-A writers
+// and the stage-B readers step k1 on lanes); LDS B->C: [j2][j3 % W][k1] with
+// pitch N+1 (stage-B writers step k1 on lanes; stage-C readers step j3 at an
+// odd stride and the next j2 row lands on the other half of the banks).
 template <int N, int S, bool LOSS>
 __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, const cx<float>* fhc,
                                            long row, int p, int t, float (&acc)[S][N]) {
   constexpr int T = N * N / S;
   constexpr int W = N / S;
   constexpr int AB = W + 1;
-  const int tb_k1 = t / W, tl = t % W;  // stage B: k1, j3 % W; stage C: j2, j3 % W
+  constexpr int BC = W * (N + 1);  // j2 row pitch of the B->C buffer
+  static_assert(N * BC <= N * N * AB, "B->C buffer must fit in the A->B allocation");
+  const int tb_k1 = t / W, tl = t % W;  // stage C: j2, j3 % W
+  const int sb_k1 = t % N, sb_j = t / N;  // stage B: k1, j3 % W
   const cx<float>* mp = a.mult + size_t(p) * N * N * N;
   const float wp = a.w[p];
   // stage A: each pencil is loaded in two halves (bounded registers in
@@ -490,18 +495,18 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const int k2 = bzk::first_stage_order<N>(r);
-      rb[k2] = lds[(k2 * N + tb_k1) * AB + tl];
+      rb[k2] = lds[(k2 * N + sb_k1) * AB + sb_j];
     }
     bzk::fft<N, 1>(rb);
     lds_barrier();
 #pragma unroll
-    for (int j2 = 0; j2 < N; ++j2) lds[(j2 * N + tb_k1) * W + tl] = rb[j2];
+    for (int j2 = 0; j2 < N; ++j2) lds[j2 * BC + sb_j * (N + 1) + sb_k1] = rb[j2];
     lds_barrier();
     cx<float> rc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const int k1 = bzk::first_stage_order<N>(r);
-      rc[k1] = lds[(tb_k1 * N + k1) * W + tl];
+      rc[k1] = lds[tb_k1 * BC + tl * (N + 1) + k1];
     }
     bzk::fft<N, 1>(rc);
     if constexpr (LOSS) {
@@ -527,11 +532,13 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 //   stage A: thread t owns pencils P = a*T + t (a < S) along k3 at
 //            (k1, k2) = (P % N, P / N);
 //   stage B: thread t owns, in every slice, the pencil along k2 at
-//            (k1, j3) = (t / W, s*W + t % W);
+//            (k1, j3) = (t % N, s*W + t / N);
 //   stage C: thread t owns, in every slice, the pencil along k1 at
 //            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
-// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride for the writers'
-// lanes along k1); LDS B->C: [j2][k1][j3 % W] (both sides step j3 on lanes).
+// LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride: the stage-A writers
+// and the stage-B readers step k1 on lanes); LDS B->C: [j2][j3 % W][k1] with
+// pitch N+1 (stage-B writers step k1 on lanes; stage-C readers step j3 at an
+// odd stride and the next j2 row lands on the other half of the banks).
 // Register budget: the paired (S = 2) kernels need up to 256 VGPRs (2 waves
 // per SIMD); N = 16 with one slice fits 4 waves per SIMD (128 VGPRs).
 template <int N, int S>
