@@ -21,6 +21,9 @@ velocity are the grid sums times dv^3.
                            + dt (Q(f^n) - P(f^n)) / (eps + beta dt)
                            + beta dt/(eps + beta dt) M^{n+1},
                M^{n+1} the Maxwellian of U^{n+1}.
+  esbgk_*      the ES-BGK operator Q_ES = nu (G[f] - f) with the corrected
+               Gaussian G of Sec. 2.2, and its first-order IMEX step solved
+               explicitly (Sec. 4.3).
 """
 from __future__ import annotations
 
@@ -96,3 +99,79 @@ def imex_euler(f: np.ndarray, tr: np.ndarray, dt: float, eps: float, plan: spect
     if project:
         q = spectral.project(q, plan.n, plan.L)
     return imex_combine(f, tr, q, dt, eps, plan.L)
+
+
+# ---------------------------------------------------------------- ES-BGK (Sec. 2.2)
+def second_moments(h: np.ndarray, n: int, L: float) -> np.ndarray:
+    """S = int v (x) v h, a symmetric 3x3 matrix."""
+    V = _grid(n, L)
+    w = V[3]
+    return np.array([[w * (V[a] * V[b] * h).sum() for b in range(3)] for a in range(3)])
+
+
+def stress(f: np.ndarray, n: int, L: float):
+    """(rho, u, Theta) with rho Theta = int (v - u) (x) (v - u) f (Sec. 2.2)."""
+    rho, u, _ = moments(f, n, L)
+    V = _grid(n, L)
+    w = V[3]
+    th = np.array([[w * ((V[a] - u[a]) * (V[b] - u[b]) * f).sum() for b in range(3)] for a in range(3)]) / rho
+    return rho, u, th
+
+
+def anisotropic_gaussian(rho: float, u, tau: np.ndarray, n: int, L: float) -> np.ndarray:
+    """G = rho / sqrt(det(2 pi Tau)) exp(-(v - u) Tau^-1 (v - u) / 2)."""
+    V1, V2, V3, _ = _grid(n, L)
+    d = np.stack([V1 - u[0], V2 - u[1], V3 - u[2]], axis=-1)
+    ti = np.linalg.inv(tau)
+    quad = np.einsum("...a,ab,...b->...", d, ti, d)
+    return rho / math.sqrt(np.linalg.det(2.0 * math.pi * tau)) * np.exp(-0.5 * quad)
+
+
+def esbgk_frequency(rho: float, T: float, beta: float, mu0: float) -> float:
+    """nu(rho, T): relaxation rate whose ES-BGK viscosity rho T / (nu (1 - beta))
+    is the hard-sphere mu = mu0 sqrt(T)."""
+    return rho * math.sqrt(T) / (mu0 * (1.0 - beta))
+
+
+def esbgk_tensor(T: float, theta: np.ndarray, beta: float) -> np.ndarray:
+    """Tau = (1 - beta) T I + beta Theta (Sec. 2.2)."""
+    return (1.0 - beta) * T * np.eye(3) + beta * theta
+
+
+def esbgk_gaussian(f: np.ndarray, n: int, L: float, beta: float) -> np.ndarray:
+    """G[f] of Sec. 2.2 from f's own density, velocity and stress."""
+    rho, u, th = stress(f, n, L)
+    T = np.trace(th) / 3.0
+    return anisotropic_gaussian(rho, u, esbgk_tensor(T, th, beta), n, L)
+
+
+def esbgk_collide(f: np.ndarray, n: int, L: float, beta: float, mu0: float) -> np.ndarray:
+    """Q_ES(f) = nu(rho, T) (G[f] - f) (Sec. 2.2)."""
+    rho, u, th = stress(f, n, L)
+    T = np.trace(th) / 3.0
+    G = anisotropic_gaussian(rho, u, esbgk_tensor(T, th, beta), n, L)
+    return esbgk_frequency(rho, T, beta, mu0) * (G - f)
+
+
+def esbgk_imex_euler(f: np.ndarray, tr: np.ndarray, dt: float, eps: float, L: float, beta: float,
+                     mu0: float) -> np.ndarray:
+    """One first-order IMEX step of the ES-BGK layer (Sec. 4.3, after Filbet
+    and Jin), solved explicitly:
+      g = f^n - dt tr;  U^{n+1} = int phi g -> rho, u, T at n+1;  nu = nu(rho, T);
+      Sigma^{n+1} = eps/(eps + (1-beta) nu dt) int v (x) v g
+                    + (1-beta) nu dt/(eps + (1-beta) nu dt) rho (T I + u (x) u);
+      Theta^{n+1} = Sigma^{n+1}/rho - u (x) u;  Tau = (1-beta) T I + beta Theta;
+      f^{n+1} = eps/(eps + nu dt) g + nu dt/(eps + nu dt) G(rho, u, Tau)."""
+    n = f.shape[0]
+    g = f - dt * tr
+    U = conserved(g, n, L)
+    rho = U[0]
+    u = U[1:4] / rho
+    T = (U[4] / rho - u @ u) / 3.0
+    nu = esbgk_frequency(rho, T, beta, mu0)
+    a = eps / (eps + (1.0 - beta) * nu * dt)
+    sigma = a * second_moments(g, n, L) + (1.0 - a) * rho * (T * np.eye(3) + np.outer(u, u))
+    theta = sigma / rho - np.outer(u, u)
+    G = anisotropic_gaussian(rho, u, esbgk_tensor(T, theta, beta), n, L)
+    c = eps / (eps + nu * dt)
+    return c * g + (1.0 - c) * G

@@ -145,3 +145,87 @@ def test_imex_penalty_uses_the_new_density():
     want = (eps * g + beta * dt * M1) / (eps + beta * dt)
     out = kinetic.imex_combine(f, tr, np.zeros_like(f), dt, eps, L)
     assert np.abs(out - want).max() <= 1e-12 * np.abs(want).max()
+
+
+# ---------------------------------------------------------------- ES-BGK
+def aniso(n, L, rho, u, cov):
+    return kinetic.anisotropic_gaussian(rho, np.asarray(u), np.asarray(cov), n, L)
+
+
+COV = np.array([[1.1, 0.2, -0.1], [0.2, 0.7, 0.05], [-0.1, 0.05, 0.9]])
+
+
+def test_anisotropic_gaussian_moments():
+    # density, velocity and stress of the sampled Gaussian are its parameters
+    n, L = 48, 10.0
+    f = aniso(n, L, 1.2, [0.3, -0.2, 0.1], COV)
+    rho, u, th = kinetic.stress(f, n, L)
+    assert abs(rho - 1.2) <= 1e-12
+    assert np.abs(u - [0.3, -0.2, 0.1]).max() <= 1e-12
+    assert np.abs(th - COV).max() <= 1e-11
+
+
+def test_esbgk_limits_of_beta():
+    n, L = 48, 10.0
+    f = aniso(n, L, 1.2, [0.3, -0.2, 0.1], COV)
+    # beta = 1: Tau = Theta, so G[f] = f and Q_ES = 0
+    assert np.abs(kinetic.esbgk_gaussian(f, n, L, 1.0) - f).max() <= 1e-11 * f.max()
+    # beta = 0: BGK, G[f] is the Maxwellian of f
+    rho, u, T = kinetic.moments(f, n, L)
+    assert abs(T - np.trace(COV) / 3) <= 1e-12
+    M = kinetic.maxwellian(rho, u, T, n, L)
+    assert np.abs(kinetic.esbgk_gaussian(f, n, L, 0.0) - M).max() <= 1e-12 * M.max()
+
+
+def test_esbgk_conserves_and_relaxes_stress():
+    # int (1, v, |v|^2) Q_ES = 0; the stress of G is (1 - beta) T I + beta Theta
+    n, L, beta = 48, 10.0, -0.5
+    f = gen.bimaxwellian_batch(1, n, L, seed=4)[0]
+    f = f + aniso(n, L, 0.3, [0.5, 0.0, -0.4], COV)
+    q = kinetic.esbgk_collide(f, n, L, beta, 1.0)
+    U = kinetic.conserved(f, n, L)
+    # exact up to the Gaussian tails cut at |v_i| = L (exp(-(L - 1)^2 / 4) ~ 1e-9 here)
+    assert np.abs(kinetic.conserved(q, n, L)).max() <= 1e-8 * np.abs(U).max()
+    rho, u, th = kinetic.stress(f, n, L)
+    T = np.trace(th) / 3
+    G = kinetic.esbgk_gaussian(f, n, L, beta)
+    _, _, thG = kinetic.stress(G, n, L)
+    assert np.abs(thG - ((1 - beta) * T * np.eye(3) + beta * th)).max() <= 1e-10
+    # nu from the viscosity relation: rho T / (nu (1 - beta)) = mu0 sqrt(T)
+    nu = kinetic.esbgk_frequency(rho, T, beta, 0.8)
+    assert abs(rho * T / (nu * (1 - beta)) - 0.8 * math.sqrt(T)) <= 1e-14
+
+
+def test_esbgk_imex_second_moments_are_consistent():
+    # the explicit solution of the implicit step: int v (x) v f^{n+1} = Sigma^{n+1}
+    # and int phi f^{n+1} = U^{n+1}
+    n, L, beta, mu0 = 48, 10.0, -0.5, 1.0
+    f = aniso(n, L, 1.0, [0.2, 0.1, -0.3], COV)
+    tr = random_transport(n, L, 8)
+    dt, eps = 0.02, 0.05
+    out = kinetic.esbgk_imex_euler(f, tr, dt, eps, L, beta, mu0)
+    g = f - dt * tr
+    U = kinetic.conserved(g, n, L)
+    assert np.abs(kinetic.conserved(out, n, L) - U).max() <= 1e-11 * np.abs(U).max()
+    rho = U[0]
+    u = U[1:4] / rho
+    T = (U[4] / rho - u @ u) / 3
+    nu = kinetic.esbgk_frequency(rho, T, beta, mu0)
+    S_out = kinetic.second_moments(out, n, L)
+    # Sigma solves Sigma = c S(g) + (1 - c) rho (Tau + u u) with Tau from Sigma (implicit)
+    c = eps / (eps + nu * dt)
+    tau = (1 - beta) * T * np.eye(3) + beta * (S_out / rho - np.outer(u, u))
+    assert np.abs(S_out - (c * kinetic.second_moments(g, n, L) + (1 - c) * rho * (tau + np.outer(u, u)))).max() \
+        <= 1e-10 * np.abs(S_out).max()
+
+
+def test_esbgk_imex_limits():
+    n, L, beta = 48, 10.0, -0.5
+    f = aniso(n, L, 1.0, [0.2, 0.1, -0.3], COV)
+    tr = random_transport(n, L, 9)
+    dt = 0.02
+    g = f - dt * tr
+    assert np.abs(kinetic.esbgk_imex_euler(f, tr, dt, 1e12, L, beta, 1.0) - g).max() <= 1e-10 * np.abs(g).max()
+    # eps -> 0: the stress relaxes to T I and f^{n+1} to the Maxwellian of U^{n+1}
+    M1, _ = kinetic.maxwellian_of_conserved(kinetic.conserved(g, n, L), n, L)
+    assert np.abs(kinetic.esbgk_imex_euler(f, tr, dt, 1e-14, L, beta, 1.0) - M1).max() <= 1e-10 * M1.max()
