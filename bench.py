@@ -214,15 +214,17 @@ def sweep(cells: int = 1024, reps: int = 3):
 
 def kinetic_run(col, f, steps: int):
     """The per-cell kinetic steps on the same batch: macroscopic fields + L1
-    distance (bz_cell_moments) and one penalised IMEX step (bz_imex_euler,
-    eq. 1002) fused with the collision evaluation.  Times from HIP events on
-    the current stream."""
+    distance (bz_cell_moments), one penalised IMEX step (bz_imex_euler,
+    eq. 1002) fused with the collision evaluation, the ES-BGK operator and its
+    IMEX step.  Times from HIP events on the current stream; compulsory bytes
+    per cell: 8n (moments), 16n (ES-BGK: f in, Q out), 24n (ES-BGK IMEX: f and
+    the transport term in, f_out out)."""
     import torch
 
     import bz_inputs as gen
     import paper_2505_03360_amd as bz
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
     mom = bz.cell_moments(f, L)
     ev[0].record()
     for _ in range(steps):
@@ -235,14 +237,31 @@ def kinetic_run(col, f, steps: int):
     for _ in range(steps):
         col.imex_euler(f, tr, 0.01, eps=0.01, out=fo)
     ev[3].record()
+    qes = bz.esbgk_collide(f, L)
+    ev[4].record()
+    for _ in range(steps):
+        bz.esbgk_collide(f, L, out=qes)
+    ev[5].record()
+    bz.esbgk_imex_euler(f, tr, L, 0.01, eps=0.01, out=fo)
+    ev[6].record()
+    for _ in range(steps):
+        bz.esbgk_imex_euler(f, tr, L, 0.01, eps=0.01, out=fo)
+    ev[7].record()
     torch.cuda.synchronize()
     mom_ms = ev[0].elapsed_time(ev[1]) / steps
     imex_ms = ev[2].elapsed_time(ev[3]) / steps
+    es_ms = ev[4].elapsed_time(ev[5]) / steps
+    esi_ms = ev[6].elapsed_time(ev[7]) / steps
     cells = f.shape[0]
     return {"moments_l1_ms": mom_ms,
             "moments_l1_compulsory_GB_s": cells * 8 * N ** 3 / (mom_ms * 1e-3) / 1e9,
             "imex_euler_ms": imex_ms, "imex_euler_cells_per_s": cells / (imex_ms * 1e-3),
-            "workload": f"{cells} cells N=32 M=32 FP32 collision + FP64 IMEX (eq. 1002), dt=0.01, eps=0.01"}
+            "esbgk_collide_ms": es_ms,
+            "esbgk_collide_compulsory_GB_s": cells * 16 * N ** 3 / (es_ms * 1e-3) / 1e9,
+            "esbgk_imex_ms": esi_ms,
+            "esbgk_imex_compulsory_GB_s": cells * 24 * N ** 3 / (esi_ms * 1e-3) / 1e9,
+            "workload": f"{cells} cells N=32; M=32 FP32 collision + FP64 IMEX (eq. 1002), dt=0.01, eps=0.01; "
+                        "ES-BGK beta=-1/2, mu0=1"}
 
 
 def main():

@@ -249,7 +249,38 @@ bz_status bz_imex_euler(const bz_plan* plan, const bz_imex_desc* desc, const dou
                         const int32_t* idx, int32_t ncells, const int32_t* ncells_dev, double* f_out,
                         int32_t flags, void* stream);
 
-/* Mask descriptor (Sec. 3.3, 4.5, Algorithm 1). */
+/*
+ * ES-BGK operator of the intermediate layer (Sec. 2.2) and its first-order
+ * IMEX step (Sec. 4.3, after Filbet and Jin), FP64, one cell per workgroup:
+ *   rho Theta = int (v-u)(x)(v-u) f,  T = tr(Theta)/3,
+ *   Tau = (1 - beta) T I + beta Theta,
+ *   G[f] = rho det(2 pi Tau)^(-1/2) exp(-(v-u) Tau^-1 (v-u) / 2),
+ *   Q_ES(f) = nu (G[f] - f),  nu = rho sqrt(T) / (mu0 (1 - beta)) (the relaxation
+ *   rate whose ES-BGK viscosity is the hard-sphere mu = mu0 sqrt(T); the paper
+ *   names nu(rho, T) without a formula).
+ * IMEX: g = f - dt tr; rho, u, T of g (the invariants of the step);
+ *   Sigma = a int v(x)v g + (1 - a) rho (T I + u(x)u), a = eps/(eps + (1-beta) nu dt);
+ *   Theta = Sigma/rho - u(x)u;  f_out = c g + (1 - c) G(rho, u, Tau), c = eps/(eps + nu dt).
+ * desc: n in {16, 24, 32, 48}, L > 0, beta < 1 (-1/2: Prandtl 2/3), mu0 > 0.
+ * f, tr: device FP64 [*][n][n][n], cell c at row idx[c] (idx NULL: row c).
+ * q / f_out: device FP64, row c or idx[c] (BZ_SCATTER).  f_out may equal f
+ * when the rows written are the rows read; q must not alias f.
+ * Asynchronous on `stream`; per-cell results do not depend on the batch.
+ */
+typedef struct {
+  int32_t n;
+  double L;
+  double beta;
+  double mu0;
+} bz_esbgk_desc;
+
+bz_status bz_esbgk_collide(const bz_esbgk_desc* desc, const double* f, const int32_t* idx, int32_t ncells,
+                           const int32_t* ncells_dev, double* q, int32_t flags, void* stream);
+bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* desc, const bz_imex_desc* imex, const double* f,
+                              const double* tr, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                              double* f_out, int32_t flags, void* stream);
+
+
 typedef struct {
   int32_t nx, ny;           /* spatial grid, arrays are row-major [iy][ix] */
   double dx, dy;            /* spacings */

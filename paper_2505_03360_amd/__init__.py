@@ -102,6 +102,10 @@ class BzImexDesc(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("eps", ctypes.c_double), ("eps_cells", ctypes.c_void_p)]
 
 
+class BzEsbgkDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("L", ctypes.c_double), ("beta", ctypes.c_double), ("mu0", ctypes.c_double)]
+
+
 class BzError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"bz error {code}: {msg}")
@@ -132,6 +136,9 @@ SIGNATURES = [
     ("bz_cell_moments", _I32, [_I32, ctypes.c_double, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(BzMomentsOut),
                                _I32, _VP]),
     ("bz_imex_euler", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_esbgk_collide", _I32, [ctypes.POINTER(BzEsbgkDesc), _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_esbgk_imex_euler", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32,
+                                   _VP, _VP, _I32, _VP]),
     ("bz_plan_last_times", _I32, [_VP, ctypes.POINTER(ctypes.c_float), _I32]),
     ("bz_realizability_mask", _I32, [ctypes.POINTER(BzMaskDesc), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -270,6 +277,17 @@ def bz_cell_moments(n: int, L: float, f: int, f_dtype: int, idx: int, ncells: in
 def bz_imex_euler(plan: int, desc: BzImexDesc, f: int, tr: int, idx: int, ncells: int, ncells_dev: int,
                   f_out: int, flags: int = 0, stream: int = 0) -> None:
     _check(lib().bz_imex_euler(plan, ctypes.byref(desc), f, tr, idx, ncells, ncells_dev, f_out, flags, stream))
+
+
+def bz_esbgk_collide(desc: BzEsbgkDesc, f: int, idx: int, ncells: int, ncells_dev: int, q: int,
+                     flags: int = 0, stream: int = 0) -> None:
+    _check(lib().bz_esbgk_collide(ctypes.byref(desc), f, idx, ncells, ncells_dev, q, flags, stream))
+
+
+def bz_esbgk_imex_euler(desc: BzEsbgkDesc, imex: BzImexDesc, f: int, tr: int, idx: int, ncells: int,
+                        ncells_dev: int, f_out: int, flags: int = 0, stream: int = 0) -> None:
+    _check(lib().bz_esbgk_imex_euler(ctypes.byref(desc), ctypes.byref(imex), f, tr, idx, ncells, ncells_dev,
+                                     f_out, flags, stream))
 
 
 def bz_plan_set_timing(plan: int, enable: bool) -> None:
@@ -426,6 +444,42 @@ def cell_moments(f, L: float, idx=None, ncells=None, ncells_dev=None, out=None, 
     fd = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
     bz_cell_moments(n, L, _ptr(f), fd, _ptr(idx), ncells, _ptr(ncells_dev), o,
                     BZ_SCATTER if scatter else 0, _stream(stream))
+    return out
+
+
+def _f64_cells(f, idx, ncells):
+    torch = _torch()
+    if f.dtype != torch.float64 or not f.is_contiguous() or not f.is_cuda:
+        raise ValueError("f must be a contiguous CUDA float64 tensor")
+    n = f.shape[-1]
+    if ncells is None:
+        ncells = idx.numel() if idx is not None else f.numel() // n ** 3
+    return n, ncells
+
+
+def esbgk_collide(f, L: float, beta: float = -0.5, mu0: float = 1.0, idx=None, ncells=None, ncells_dev=None,
+                  out=None, scatter=False, stream=None):
+    """Q_ES(f) = nu (G[f] - f) for a batch of cells (bz_esbgk_collide)."""
+    torch = _torch()
+    n, ncells = _f64_cells(f, idx, ncells)
+    if out is None:
+        out = torch.empty((ncells, n, n, n), dtype=torch.float64, device=f.device)
+    bz_esbgk_collide(BzEsbgkDesc(n, L, beta, mu0), _ptr(f), _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
+                     BZ_SCATTER if scatter else 0, _stream(stream))
+    return out
+
+
+def esbgk_imex_euler(f, tr, L: float, dt: float, eps: float = 0.0, eps_cells=None, beta: float = -0.5,
+                     mu0: float = 1.0, idx=None, ncells=None, ncells_dev=None, out=None, scatter=False,
+                     stream=None):
+    """One first-order IMEX step of the ES-BGK layer (bz_esbgk_imex_euler)."""
+    torch = _torch()
+    n, ncells = _f64_cells(f, idx, ncells)
+    if out is None:
+        out = torch.empty((ncells, n, n, n), dtype=torch.float64, device=f.device)
+    bz_esbgk_imex_euler(BzEsbgkDesc(n, L, beta, mu0), BzImexDesc(dt, eps, _ptr(eps_cells)), _ptr(f), _ptr(tr),
+                        _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out), BZ_SCATTER if scatter else 0,
+                        _stream(stream))
     return out
 
 

@@ -3,16 +3,20 @@
 // 3.3), and the parameters of the penalised IMEX update of the Boltzmann layer
 // (Sec. 4.4, eq. 1002).
 //
-// One workgroup of 256 threads per cell.  Each thread accumulates a strided
-// subset of the nodes, then the partial sums are combined across the wave
-// (butterfly) and across the four waves in a fixed order, so the result of a
-// cell does not depend on the batch it is in.
+// One workgroup of 1024 threads per cell (16 waves per CU keep enough loads in
+// flight for these HBM-bound sums).  Each thread accumulates a strided subset
+// of the nodes, then the partial sums are combined across the wave
+// (butterfly) and across the sixteen waves in a fixed order, so the result of
+// a cell does not depend on the batch it is in.
 #include "bz_internal.hpp"
 #include "kinetic.hpp"
 
+#include <cmath>
+
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
 
 __device__ __forceinline__ int live_cells(int ncells, const int32_t* ncells_dev) {
   int c = ncells;
@@ -34,10 +38,14 @@ __device__ __forceinline__ void block_sum(double (&m)[K], double* red) {
     for (int o = 32; o > 0; o >>= 1) m[k] += __shfl_xor(m[k], o);
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < K; ++k) red[k * 4 + wv] = m[k];
+    for (int k = 0; k < K; ++k) red[k * kWaves + wv] = m[k];
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < K; ++k) m[k] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+  for (int k = 0; k < K; ++k) {
+    double x = red[k * kWaves];
+    for (int w = 1; w < kWaves; ++w) x += red[k * kWaves + w];
+    m[k] = x;
+  }
   __syncthreads();
 }
 
@@ -60,7 +68,7 @@ __device__ __forceinline__ double node(int i, double dv) { return double(i - N /
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_moments(MomArgs a) {
   constexpr int N3 = N * N * N;
-  __shared__ double red[5 * 4];
+  __shared__ double red[5 * kWaves];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -123,7 +131,7 @@ struct ParArgs {
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_imex_params(ParArgs a) {
   constexpr int N3 = N * N * N;
-  __shared__ double red[10 * 4];
+  __shared__ double red[10 * kWaves];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -165,6 +173,100 @@ __global__ __launch_bounds__(kThreads) void k_imex_params(ParArgs a) {
       if (h == 1) p[10] = 2.0 * M_PI * rho;
     }
     p[11] = 0.0;
+  }
+}
+
+struct EsArgs {
+  int ncells;
+  const int32_t* ncells_dev;
+  const int32_t* idx;
+  int scatter;
+  const double* f;
+  const double* tr;         // IMEX: transport term (rows as f)
+  const double* eps_cells;  // IMEX: Knudsen number per row, or null
+  double eps, dt;           // IMEX
+  double beta, mu0, dv;
+  double* out;
+};
+
+// ES-BGK (Sec. 2.2), one cell per workgroup.
+//   collision:  Q_ES = nu (G[f] - f), G from f's density, velocity and stress;
+//   IMEX (Sec. 4.3): with g = f - dt tr and its rho, u, T (invariants of the
+//     step), Sigma = a S(g) + (1 - a) rho (T I + u u), a = eps / (eps + (1 - beta)
+//     nu dt), Theta = Sigma / rho - u u, and f^{n+1} = c g + (1 - c) G,
+//     c = eps / (eps + nu dt).
+// G = rho (2 pi)^(-3/2) det(Tau)^(-1/2) exp(-(v-u) Tau^-1 (v-u) / 2),
+// Tau = (1 - beta) T I + beta Theta; nu = rho sqrt(T) / (mu0 (1 - beta)).
+template <int N, bool IMEX>
+__global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
+  constexpr int N3 = N * N * N;
+  __shared__ double red[10 * kWaves];
+  const int c = blockIdx.x;
+  if (c >= live_cells(a.ncells, a.ncells_dev)) return;
+  const int t = threadIdx.x;
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+  const double* f = a.f + size_t(row) * N3;
+  const double* tr = IMEX ? a.tr + size_t(row) * N3 : nullptr;
+  auto h = [&](int j) -> double {
+    if constexpr (IMEX) return f[j] - a.dt * tr[j];
+    else return f[j];
+  };
+  // sums of h, v h, v_a v_b h (11, 22, 33, 12, 13, 23)
+  double m[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = t; j < N3; j += kThreads) {
+    const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
+    const double hj = h(j);
+    m[0] += hj;
+    m[1] += v1 * hj;
+    m[2] += v2 * hj;
+    m[3] += v3 * hj;
+    m[4] += v1 * v1 * hj;
+    m[5] += v2 * v2 * hj;
+    m[6] += v3 * v3 * hj;
+    m[7] += v1 * v2 * hj;
+    m[8] += v1 * v3 * hj;
+    m[9] += v2 * v3 * hj;
+  }
+  block_sum<10>(m, red);
+  const double w = a.dv * a.dv * a.dv;
+  const double rho = w * m[0];
+  const double u[3] = {m[1] / m[0], m[2] / m[0], m[3] / m[0]};
+  // Theta_ab = S_ab / rho - u_a u_b for the pairs (11, 22, 33, 12, 13, 23)
+  constexpr int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+  double th[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) th[k] = m[4 + k] / m[0] - u[A[k]] * u[B[k]];
+  const double T = (th[0] + th[1] + th[2]) / 3.0;
+  const double nu = rho * sqrt(T) / (a.mu0 * (1.0 - a.beta));
+  [[maybe_unused]] double cmix = 0.0;
+  if constexpr (IMEX) {
+    const double eps = a.eps_cells ? a.eps_cells[row] : a.eps;
+    const double am = eps / (eps + (1.0 - a.beta) * nu * a.dt);
+    // Sigma / rho - u u with Sigma = am S(g) + (1 - am) rho (T I + u u)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) th[k] = am * th[k] + (1.0 - am) * (k < 3 ? T : 0.0);
+    cmix = eps / (eps + nu * a.dt);
+  }
+  double tau[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) tau[k] = a.beta * th[k] + (k < 3 ? (1.0 - a.beta) * T : 0.0);
+  // inverse of the symmetric Tau by cofactors
+  const double t11 = tau[0], t22 = tau[1], t33 = tau[2], t12 = tau[3], t13 = tau[4], t23 = tau[5];
+  const double c11 = t22 * t33 - t23 * t23, c22 = t11 * t33 - t13 * t13, c33 = t11 * t22 - t12 * t12;
+  const double c12 = t13 * t23 - t12 * t33, c13 = t12 * t23 - t13 * t22, c23 = t12 * t13 - t11 * t23;
+  const double det = t11 * c11 + t12 * c12 + t13 * c13;
+  const double id = 1.0 / det;
+  const double i11 = c11 * id, i22 = c22 * id, i33 = c33 * id, i12 = c12 * id, i13 = c13 * id, i23 = c23 * id;
+  const double cg = rho / sqrt(8.0 * M_PI * M_PI * M_PI * det);
+  double* out = a.out + size_t(a.scatter ? row : long(c)) * N3;
+  for (int j = t; j < N3; j += kThreads) {
+    const double d1 = node<N>(j / (N * N), a.dv) - u[0], d2 = node<N>((j / N) % N, a.dv) - u[1],
+                 d3 = node<N>(j % N, a.dv) - u[2];
+    const double quad = i11 * d1 * d1 + i22 * d2 * d2 + i33 * d3 * d3 +
+                        2.0 * (i12 * d1 * d2 + i13 * d1 * d3 + i23 * d2 * d3);
+    const double G = cg * exp(-0.5 * quad);
+    if constexpr (IMEX) out[j] = cmix * h(j) + (1.0 - cmix) * G;
+    else out[j] = nu * (G - f[j]);
   }
 }
 
@@ -228,4 +330,86 @@ extern "C" bz_status bz_cell_moments(int32_t n, double L, const void* f, int32_t
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_cell_moments: launch failed: %s", hipGetErrorString(e));
   return BZ_OK;
+}
+
+namespace {
+
+bz_status esbgk_check(const char* who, const bz_esbgk_desc* d, int32_t ncells, int32_t flags, const int32_t* idx) {
+  if (!d) return bz::fail(BZ_ERR_ARG, "%s: null descriptor", who);
+  if (!bz::kinetic_n_supported(d->n)) return bz::fail(BZ_ERR_UNSUPPORTED, "%s: n=%d", who, d->n);
+  if (!(d->L > 0.0)) return bz::fail(BZ_ERR_ARG, "%s: L must be > 0", who);
+  if (!(d->beta < 1.0) || !std::isfinite(d->beta)) return bz::fail(BZ_ERR_ARG, "%s: beta must be < 1", who);
+  if (!(d->mu0 > 0.0)) return bz::fail(BZ_ERR_ARG, "%s: mu0 must be > 0", who);
+  if (ncells < 0) return bz::fail(BZ_ERR_ARG, "%s: ncells < 0", who);
+  if (flags & ~int32_t(BZ_SCATTER)) return bz::fail(BZ_ERR_ARG, "%s: unknown flags", who);
+  if ((flags & BZ_SCATTER) && !idx) return bz::fail(BZ_ERR_ARG, "%s: BZ_SCATTER needs idx", who);
+  return BZ_OK;
+}
+
+template <bool IMEX>
+bz_status esbgk_launch(const bz_esbgk_desc* d, const EsArgs& a, int ncells, void* stream, const char* who) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(static_cast<unsigned>(ncells)), block(kThreads);
+  switch (d->n) {
+    case 16: hipLaunchKernelGGL((k_esbgk<16, IMEX>), grid, block, 0, s, a); break;
+    case 24: hipLaunchKernelGGL((k_esbgk<24, IMEX>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_esbgk<32, IMEX>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_esbgk<48, IMEX>), grid, block, 0, s, a); break;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+  return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" bz_status bz_esbgk_collide(const bz_esbgk_desc* d, const double* f, const int32_t* idx, int32_t ncells,
+                                      const int32_t* ncells_dev, double* q, int32_t flags, void* stream) {
+  bz::clear_error();
+  bz_status st = esbgk_check("bz_esbgk_collide", d, ncells, flags, idx);
+  if (st != BZ_OK) return st;
+  if (ncells == 0) return BZ_OK;
+  if (!f || !q) return bz::fail(BZ_ERR_ARG, "bz_esbgk_collide: null f or q");
+  if (q == f) return bz::fail(BZ_ERR_ARG, "bz_esbgk_collide: q must not alias f");
+  EsArgs a{};
+  a.ncells = ncells;
+  a.ncells_dev = ncells_dev;
+  a.idx = idx;
+  a.scatter = (flags & BZ_SCATTER) != 0;
+  a.f = f;
+  a.beta = d->beta;
+  a.mu0 = d->mu0;
+  a.dv = 2.0 * d->L / d->n;
+  a.out = q;
+  return esbgk_launch<false>(d, a, ncells, stream, "bz_esbgk_collide");
+}
+
+extern "C" bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* d, const bz_imex_desc* im, const double* f,
+                                         const double* tr, const int32_t* idx, int32_t ncells,
+                                         const int32_t* ncells_dev, double* f_out, int32_t flags, void* stream) {
+  bz::clear_error();
+  bz_status st = esbgk_check("bz_esbgk_imex_euler", d, ncells, flags, idx);
+  if (st != BZ_OK) return st;
+  if (!im) return bz::fail(BZ_ERR_ARG, "bz_esbgk_imex_euler: null IMEX descriptor");
+  if (!(im->dt > 0.0) || !std::isfinite(im->dt)) return bz::fail(BZ_ERR_ARG, "bz_esbgk_imex_euler: dt must be > 0");
+  if (!im->eps_cells && !(im->eps > 0.0)) return bz::fail(BZ_ERR_ARG, "bz_esbgk_imex_euler: eps must be > 0");
+  if (ncells == 0) return BZ_OK;
+  if (!f || !tr || !f_out) return bz::fail(BZ_ERR_ARG, "bz_esbgk_imex_euler: null f, tr or f_out");
+  if (f_out == f && idx && !(flags & BZ_SCATTER))
+    return bz::fail(BZ_ERR_ARG, "bz_esbgk_imex_euler: in place with idx needs BZ_SCATTER");
+  EsArgs a{};
+  a.ncells = ncells;
+  a.ncells_dev = ncells_dev;
+  a.idx = idx;
+  a.scatter = (flags & BZ_SCATTER) != 0;
+  a.f = f;
+  a.tr = tr;
+  a.eps_cells = im->eps_cells;
+  a.eps = im->eps;
+  a.dt = im->dt;
+  a.beta = d->beta;
+  a.mu0 = d->mu0;
+  a.dv = 2.0 * d->L / d->n;
+  a.out = f_out;
+  return esbgk_launch<true>(d, a, ncells, stream, "bz_esbgk_imex_euler");
 }

@@ -138,3 +138,48 @@ def test_imex_equilibrium_and_conservation():
         U1 = kinetic.conserved(f[c] - 0.01 * tr[c], n, L)
         assert np.abs(kinetic.conserved(out[c], n, L) - U1).max() <= 1e-6 * np.abs(U1).max()
     col.close()
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 48])
+@pytest.mark.parametrize("beta", [-0.5, 0.0, 0.5])
+def test_esbgk_collide_against_oracle(n, beta):
+    import paper_2505_03360_amd as bz
+    print("case esbgk", n, beta, flush=True)
+    L, mu0 = 8.0, 0.9
+    f = gen.shock_batch(5, n, L, seed=40 + n)
+    rows = [3, 0, 4]
+    idx = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    q = bz.esbgk_collide(torch.from_numpy(f).cuda(), L, beta, mu0, idx=idx).cpu().numpy()
+    for c, r in enumerate(rows):
+        ref = kinetic.esbgk_collide(f[r], n, L, beta, mu0)
+        rho, u, th = kinetic.stress(f[r], n, L)
+        nu = kinetic.esbgk_frequency(rho, np.trace(th) / 3, beta, mu0)
+        floor = max(np.linalg.norm(ref), 0.05 * nu * np.linalg.norm(f[r]))
+        err = np.linalg.norm(q[c] - ref) / floor
+        print(f"  row {r}: err {err:.3e}", flush=True)
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_esbgk_imex_against_oracle(n):
+    import paper_2505_03360_amd as bz
+    print("case esbgk imex", n, flush=True)
+    L, dt, beta, mu0 = 8.0, 0.01, -0.5, 1.0
+    f = gen.shock_batch(4, n, L, seed=50 + n)
+    tr = transport(f, n, L, 11)
+    eps_rows = np.array([0.01, 1e-4, 0.2, 3.0])
+    rows = [2, 0, 3]
+    ft, trt = torch.from_numpy(f).cuda(), torch.from_numpy(tr).cuda()
+    idx = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    out = bz.esbgk_imex_euler(ft, trt, L, dt, eps_cells=torch.from_numpy(eps_rows).cuda(), beta=beta, mu0=mu0,
+                              idx=idx).cpu().numpy()
+    for c, r in enumerate(rows):
+        ref = kinetic.esbgk_imex_euler(f[r], tr[r], dt, eps_rows[r], L, beta, mu0)
+        assert np.linalg.norm(out[c] - ref) <= 1e-12 * np.linalg.norm(ref)
+    # in place over the listed rows with a scalar eps
+    bz.esbgk_imex_euler(ft, trt, L, dt, eps=0.05, beta=beta, mu0=mu0, idx=idx, out=ft, scatter=True)
+    got = ft.cpu().numpy()
+    for r in rows:
+        ref = kinetic.esbgk_imex_euler(f[r], tr[r], dt, 0.05, L, beta, mu0)
+        assert np.linalg.norm(got[r] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.array_equal(got[1], f[1])

@@ -125,3 +125,25 @@ def test_moments_and_imex_validation():
         bz.bz_imex_euler(p, bz.BzImexDesc(0.01, 0.1, None), 0, 0, 0, 1, 0, 0)
     assert e.value.code == bz.BZ_ERR_STATE  # not bound
     bz.bz_plan_destroy(p)
+
+
+def test_esbgk_validation():
+    imex = bz.BzImexDesc(0.01, 0.1, None)
+    for desc, code in ((bz.BzEsbgkDesc(20, 8.0, -0.5, 1.0), bz.BZ_ERR_UNSUPPORTED),
+                       (bz.BzEsbgkDesc(32, 8.0, 1.0, 1.0), bz.BZ_ERR_ARG),
+                       (bz.BzEsbgkDesc(32, 8.0, -0.5, 0.0), bz.BZ_ERR_ARG),
+                       (bz.BzEsbgkDesc(32, -1.0, -0.5, 1.0), bz.BZ_ERR_ARG)):
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_esbgk_collide(desc, 0, 0, 4, 0, 0)
+        assert e.value.code == code
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_esbgk_imex_euler(desc, imex, 0, 0, 0, 4, 0, 0)
+        assert e.value.code == code
+    good = bz.BzEsbgkDesc(32, 8.0, -0.5, 1.0)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_esbgk_imex_euler(good, bz.BzImexDesc(0.0, 0.1, None), 0, 0, 0, 4, 0, 0)
+    assert e.value.code == bz.BZ_ERR_ARG
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_esbgk_collide(good, 0, 0, 4, 0, 0)  # null pointers
+    assert e.value.code == bz.BZ_ERR_ARG
+    bz.bz_esbgk_collide(good, 0, 0, 0, 0, 0)  # empty batch
