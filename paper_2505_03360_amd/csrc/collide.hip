@@ -376,15 +376,15 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   // other slices stay in registers until their turn.
   cx<float> rest[S > 1 ? S : 1][S > 1 ? N - W : 1];
   lds_barrier();  // LDS free: the previous pass's stage C has read it
-  if constexpr (S == 2) {
-    // Mirror pairing.  With M = a + ib (a, b real and even in k) and F of a
+  if constexpr (S == 2 && !LOSS) {
+    // Mirror pairing (gain passes).  With M = a + ib (a, b real and even in k) and F of a
     // real f (Hermitian), thread (k1, k2), k2 < N/2, transforms U = a F and
     // V = b F along k3 once; then pencil (k1, k2) is IDFT(X) = U^ + i V^ and
     // its mirror (-k1, -k2), whose X(k3) = M(-k3) conj(F(-k3)), is
     // conj(U^) + i conj(V^).  One set of loads and two transforms give both.
     // Row k2 = 0 mirrors onto itself: its threads take row N/2 instead, which
-    // is zero in the gain passes (the multipliers vanish on the Nyquist
-    // planes) and transformed directly in the loss pass.
+    // is zero (the gain multipliers vanish on the Nyquist planes).  The loss
+    // pass, whose multiplier is not zero there, takes the unpaired path.
     const int k1 = t % N, k2 = t / N;
     const bool row0 = k2 == 0;
     const int k1b = row0 ? k1 : (N - k1) % N;
@@ -407,25 +407,8 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     }
     bzk::fft<N, 1>(u);
     bzk::fft<N, 1>(v);
-    cx<float> xr[LOSS ? N : 1];  // loss pass: row N/2 pencil of the row-0 threads
-    if constexpr (LOSS) {
-      if (row0) {
-        const gptr<cx<float>> fr = opaque_global(fhc + size_t(N / 2) * N * N + k1);
-        const gptr<cx<float>> mr = opaque_global(mp + size_t(N / 2) * N * N + k1);
-#pragma unroll
-        for (int k3 = 0; k3 < N; ++k3) {
-          const cx<float> F = fr[k3 * N], Mv = mr[k3 * N];
-          xr[k3] = {Mv.x * F.x - Mv.y * F.y, Mv.x * F.y + Mv.y * F.x};
-        }
-        bzk::fft<N, 1>(xr);
-      }
-    }
     auto out_b = [&](int j) -> cx<float> {
-      if constexpr (LOSS) {
-        if (row0) return xr[j];
-      } else {
-        if (row0) return cx<float>{0.0f, 0.0f};
-      }
+      if (row0) return cx<float>{0.0f, 0.0f};
       return cx<float>{u[j].x + v[j].y, v[j].x - u[j].y};
     };
 #pragma unroll
@@ -447,18 +430,38 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     // Opaque per-pass bases: keeps the compiler from hoisting the n
     // per-element addresses out of the pass loop (they would occupy 2n
     // registers); loads then use base + immediate offsets.
-    const gptr<cx<float>> fb = opaque_global(fhc + off);
     const gptr<cx<float>> mb = opaque_global(mp + off);
     cx<float> x[N];
+    if constexpr (S == 2) {
+      // loss pass of the paired kernels: fhat holds rows k2 <= N/2 only; a row
+      // above is read as its Hermitian mirror, fhat(k) = conj fhat(-k)
+      const bool mir = k2 > N / 2;
+      const size_t moff = size_t(mir ? N - k2 : k2) * N * N + (mir ? (N - k1) % N : k1);
+      const gptr<cx<float>> fb = opaque_global(fhc + moff);
+      const float sg = mir ? -1.0f : 1.0f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
-        const cx<float> F = fb[k3 * N];
-        const cx<float> M = mb[k3 * N];
-        x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+        for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+          const cx<float> Fr = fb[(mir ? (N - k3) % N : k3) * N];
+          const cx<float> F = {Fr.x, sg * Fr.y};
+          const cx<float> M = mb[k3 * N];
+          x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      const gptr<cx<float>> fb = opaque_global(fhc + off);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+          const cx<float> F = fb[k3 * N];
+          const cx<float> M = mb[k3 * N];
+          x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     bzk::fft<N, 1>(x);
 #pragma unroll
@@ -476,7 +479,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
       for (int q = 0; q < S; ++q) {
         int k1, k2;
-        if constexpr (S == 2) {
+        if constexpr (S == 2 && !LOSS) {
           const int ka = t % N, kb = t / N;
           k1 = q == 0 ? ka : (kb == 0 ? ka : (N - ka) % N);
           k2 = q == 0 ? kb : (kb == 0 ? N / 2 : N - kb);
@@ -876,7 +879,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fw.idx = idx;
       fw.fh = a.fh;
       fw.fh_stride = a.fh_stride;
-      fw.mirror = p->slices == 1 ? 1 : 0;  // the paired (two-slice) kernels read rows 0..N/2 only
+      fw.mirror = p->slices == 1 ? 1 : 0;  // the one-slice kernels read every row
       if (p->n == 32) launch_fwd_fused<32>(fw, ncells, s);
       else if (p->n == 16) launch_fwd_fused<16>(fw, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
