@@ -226,6 +226,15 @@ __device__ __forceinline__ gptr<T> opaque_global(const T* p) {
 
 // Workgroup barrier that orders LDS traffic only: global loads issued before
 // it stay in flight (a full __syncthreads would wait for them).
+// Orders one wave's LDS accesses across its lanes (the wave runs in lockstep;
+// this only keeps the compiler from moving LDS accesses across it and waits
+// for the wave's outstanding LDS operations).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
@@ -354,28 +363,30 @@ __global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
 //   stage B: thread t owns, in every slice, the pencil along k2 at
 //            (k1, j3) = (t % N, s*W + t / N);
 //   stage C: thread t owns, in every slice, the pencil along k1 at
-//            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
+//            (j2, j3) = (t % N, s*W + t / N) and keeps its n products.
 // LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride: the stage-A writers
-// and the stage-B readers step k1 on lanes); LDS B->C: [j2][j3 % W][k1] with
-// pitch N+1 (stage-B writers step k1 on lanes; stage-C readers step j3 at an
-// odd stride and the next j2 row lands on the other half of the banks).
+// and the stage-B readers step k1 on lanes).  B->C reuses the slots of the
+// wave's own planes, (j2, k1) at row (N+1) j2 + k1 (N-1 rows beyond the A->B
+// data): a wave synchronises only with itself between stages B and C.
 template <int N, int S, bool LOSS>
 __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, const cx<float>* fhc,
                                            long row, int p, int t, float (&acc)[S][N]) {
   constexpr int T = N * N / S;
   constexpr int W = N / S;
   constexpr int AB = W + 1;
-  constexpr int BC = W * (N + 1);  // j2 row pitch of the B->C buffer
-  static_assert(N * BC <= N * N * AB, "B->C buffer must fit in the A->B allocation");
-  const int tb_k1 = t / W, tl = t % W;  // stage C: j2, j3 % W
-  const int sb_k1 = t % N, sb_j = t / N;  // stage B: k1, j3 % W
+  static_assert(64 % N == 0 && W % (64 / N) == 0, "a wave owns whole j3 planes");
+  // stage B: lane (k1, j3 % W) = (t % N, t / N); stage C: lane (j2, j3 % W) = (t % N, t / N).
+  // A wave's 64 lanes cover 64/N whole j3 planes, so B -> C stays inside the wave.
+  const int tk = t % N, tj = t / N;
   const cx<float>* mp = a.mult + size_t(p) * N * N * N;
   const float wp = a.w[p];
   // stage A: each pencil is loaded in two halves (bounded registers in
   // flight), transformed, and its slice-0 outputs go to LDS at once; the
   // other slices stay in registers until their turn.
+  // The loads and transforms of stage A touch registers only: a wave runs
+  // them while other waves are still in the previous pass's stage C, and
+  // waits (LDS free) only before its first LDS write.
   cx<float> rest[S > 1 ? S : 1][S > 1 ? N - W : 1];
-  lds_barrier();  // LDS free: the previous pass's stage C has read it
   if constexpr (S == 2 && !LOSS) {
     // Mirror pairing (gain passes).  With M = a + ib (a, b real and even in k) and F of a
     // real f (Hermitian), thread (k1, k2), k2 < N/2, transforms U = a F and
@@ -411,6 +422,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       if (row0) return cx<float>{0.0f, 0.0f};
       return cx<float>{u[j].x + v[j].y, v[j].x - u[j].y};
     };
+    lds_barrier();  // LDS free: every wave's previous stage C has read it
 #pragma unroll
     for (int j = 0; j < W; ++j) {
       lds[(k2 * N + k1) * AB + j] = cx<float>{u[j].x - v[j].y, u[j].y + v[j].x};
@@ -464,6 +476,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       }
     }
     bzk::fft<N, 1>(x);
+    if (q == 0) lds_barrier();  // LDS free: every wave's previous stage C has read it
 #pragma unroll
     for (int j = 0; j < W; ++j) lds[(k2 * N + k1) * AB + j] = x[j];
     if constexpr (S > 1) {
@@ -498,23 +511,27 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const int k2 = bzk::first_stage_order<N>(r);
-      rb[k2] = lds[(k2 * N + sb_k1) * AB + sb_j];
+      rb[k2] = lds[(k2 * N + tk) * AB + tj];
     }
     bzk::fft<N, 1>(rb);
-    lds_barrier();
+    // B -> C inside the wave: the wave has read every slot of its planes, and
+    // writes (j2, k1) to row (N+1) j2 + k1 of the same planes (an injective
+    // map; the row's residue j2 + k1 mod 32 keeps the writes, lanes on k1,
+    // and the reads below, lanes on j2, on distinct banks)
+    wave_lds_sync();
 #pragma unroll
-    for (int j2 = 0; j2 < N; ++j2) lds[j2 * BC + sb_j * (N + 1) + sb_k1] = rb[j2];
-    lds_barrier();
+    for (int j2 = 0; j2 < N; ++j2) lds[((N + 1) * j2 + tk) * AB + tj] = rb[j2];
+    wave_lds_sync();
     cx<float> rc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const int k1 = bzk::first_stage_order<N>(r);
-      rc[k1] = lds[tb_k1 * BC + tl * (N + 1) + k1];
+      rc[k1] = lds[((N + 1) * tk + k1) * AB + tj];
     }
     bzk::fft<N, 1>(rc);
     if constexpr (LOSS) {
       // acc -= (sL f - Im) Re with the exact input f
-      const size_t fo = size_t(row) * N * N * N + size_t(tb_k1) * N + s * W + tl;
+      const size_t fo = size_t(row) * N * N * N + size_t(tk) * N + s * W + tj;
       if (a.f_fp32) {
         const float* fp = static_cast<const float*>(a.f) + fo;
 #pragma unroll
@@ -537,11 +554,11 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 //   stage B: thread t owns, in every slice, the pencil along k2 at
 //            (k1, j3) = (t % N, s*W + t / N);
 //   stage C: thread t owns, in every slice, the pencil along k1 at
-//            (j2, j3) = (t / W, s*W + t % W) and keeps its n products.
+//            (j2, j3) = (t % N, s*W + t / N) and keeps its n products.
 // LDS A->B: [k2][k1][j3 % W] padded to W+1 (odd stride: the stage-A writers
-// and the stage-B readers step k1 on lanes); LDS B->C: [j2][j3 % W][k1] with
-// pitch N+1 (stage-B writers step k1 on lanes; stage-C readers step j3 at an
-// odd stride and the next j2 row lands on the other half of the banks).
+// and the stage-B readers step k1 on lanes).  B->C reuses the slots of the
+// wave's own planes, (j2, k1) at row (N+1) j2 + k1 (N-1 rows beyond the A->B
+// data): a wave synchronises only with itself between stages B and C.
 // Register budget: the paired (S = 2) kernels need up to 256 VGPRs (2 waves
 // per SIMD); N = 16 with one slice fits 4 waves per SIMD (128 VGPRs).
 template <int N, int S>
@@ -551,7 +568,7 @@ template <int N, int S, bool IMEX>
 __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collide_fused(FusedArgs a) {
   constexpr int W = N / S;
   constexpr int AB = W + 1;
-  __shared__ cx<float> lds[N * N * AB];
+  __shared__ cx<float> lds[(N * N + N - 1) * AB];
   const int cell = blockIdx.x / a.chunks;
   const int chunk = blockIdx.x % a.chunks;
   if (cell >= live_count(a.ncells, a.ncells_dev)) return;
@@ -568,7 +585,7 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
   const int gain_end = p1 < a.m1 - 1 ? p1 : a.m1 - 1;
   for (int p = p0; p < gain_end; ++p) fused_pass<N, S, false>(a, lds, fhc, row, p, t, acc);
   if (p1 == a.m1) fused_pass<N, S, true>(a, lds, fhc, row, a.m1 - 1, t, acc);
-  const int j2 = t / W, tl = t % W;
+  const int j2 = t % N, tl = t / N;  // this thread's stage-C (j2, j3 % W)
   if (a.fuse_project) {
     // Q = C acc; moments m = sum_j (1, v1, v2, v3, |v|^2) Q_j in FP64 with a
     // fixed reduction order (per thread, then across the wave, then across
