@@ -21,6 +21,9 @@ velocity are the grid sums times dv^3.
                            + dt (Q(f^n) - P(f^n)) / (eps + beta dt)
                            + beta dt/(eps + beta dt) M^{n+1},
                M^{n+1} the Maxwellian of U^{n+1}.
+  pr222_step   the same penalised splitting integrated with the second-order
+               PR(2,2,2) IMEX Runge-Kutta tableaux (Sec. 4.3), transport given
+               as a function of the stage value.
   esbgk_*      the ES-BGK operator Q_ES = nu (G[f] - f) with the corrected
                Gaussian G of Sec. 2.2, and its first-order IMEX step solved
                explicitly (Sec. 4.3).
@@ -175,3 +178,60 @@ def esbgk_imex_euler(f: np.ndarray, tr: np.ndarray, dt: float, eps: float, L: fl
     G = anisotropic_gaussian(rho, u, esbgk_tensor(T, theta, beta), n, L)
     c = eps / (eps + nu * dt)
     return c * g + (1.0 - c) * G
+
+
+# ---------------------------------------------------------------- PR(2,2,2) (Sec. 4.3-4.4)
+PR_C = 1.0 / math.sqrt(2.0)
+PR_DELTA = 1.0 - 1.0 / (2.0 * PR_C)
+# explicit tableau (c~, A~, w~) and implicit tableau (c, A, w) of PR(2,2,2)
+PR_A_EXP = np.array([[0.0, 0.0], [1.0, 0.0]])
+PR_W_EXP = np.array([0.5, 0.5])
+PR_A_IMP = np.array([[1.0 - PR_C, 0.0], [PR_C - PR_DELTA, PR_DELTA]])
+PR_W_IMP = np.array([0.5, 0.5])
+
+
+def penalty_solve(r: np.ndarray, h: float, eps: float, L: float) -> np.ndarray:
+    """Solution Y of Y = r + (h / eps) P(Y), P(Y) = beta (M[Y] - Y), beta = 2 pi rho:
+    P conserves (1, v, |v|^2), so M[Y] = M[r] and rho(Y) = rho(r), and
+    Y = (eps r + h beta M[r]) / (eps + h beta)."""
+    n = r.shape[0]
+    M, rho = maxwellian_of_conserved(conserved(r, n, L), n, L)
+    beta = 2.0 * math.pi * rho
+    return (eps * r + h * beta * M) / (eps + h * beta)
+
+
+def penalty(y: np.ndarray, L: float) -> np.ndarray:
+    """P(y) = beta (M[y] - y), beta = 2 pi rho(y) (the implicit part of the penalised scheme)."""
+    n = y.shape[0]
+    M, rho = maxwellian_of_conserved(conserved(y, n, L), n, L)
+    return 2.0 * math.pi * rho * (M - y)
+
+
+def pr222_step(y: np.ndarray, transport, dt: float, eps: float, plan: spectral.Plan,
+               project: bool = True) -> np.ndarray:
+    """One PR(2,2,2) step of y' = q(y) + g(y)/eps with the explicit part
+    q(y) = -transport(y) + (Q(y) - P(y))/eps and the implicit part g = P,
+    following the IMEX Runge-Kutta form of Sec. 4.3 with the tableaux printed
+    there (C = 1/sqrt 2); each implicit stage is solved by penalty_solve."""
+    L = plan.L
+
+    def Q(z):
+        q = spectral.collide(z, plan)
+        return spectral.project(q, plan.n, L) if project else q
+
+    def q_exp(z):
+        return -transport(z) + (Q(z) - penalty(z, L)) / eps
+
+    Y, qs, gs = [], [], []
+    for i in range(2):
+        r = y.copy()
+        for j in range(i):
+            r = r + dt * PR_A_EXP[i, j] * qs[j] + dt * PR_A_IMP[i, j] * gs[j] / eps
+        Yi = penalty_solve(r, dt * PR_A_IMP[i, i], eps, L)
+        Y.append(Yi)
+        qs.append(q_exp(Yi))
+        gs.append(penalty(Yi, L))
+    out = y.copy()
+    for i in range(2):
+        out = out + dt * PR_W_EXP[i] * qs[i] + dt * PR_W_IMP[i] * gs[i] / eps
+    return out

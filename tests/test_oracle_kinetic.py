@@ -229,3 +229,67 @@ def test_esbgk_imex_limits():
     # eps -> 0: the stress relaxes to T I and f^{n+1} to the Maxwellian of U^{n+1}
     M1, _ = kinetic.maxwellian_of_conserved(kinetic.conserved(g, n, L), n, L)
     assert np.abs(kinetic.esbgk_imex_euler(f, tr, dt, 1e-14, L, beta, 1.0) - M1).max() <= 1e-10 * M1.max()
+
+
+# ---------------------------------------------------------------- PR(2,2,2)
+def test_pr222_tableaux_order_conditions():
+    # both tableaux are second order and the pair satisfies the coupling conditions
+    Ae, we, Ai, wi = kinetic.PR_A_EXP, kinetic.PR_W_EXP, kinetic.PR_A_IMP, kinetic.PR_W_IMP
+    ce, ci = Ae.sum(axis=1), Ai.sum(axis=1)
+    assert np.allclose(ci, [1 - kinetic.PR_C, kinetic.PR_C]) and np.allclose(ce, [0.0, 1.0])
+    for w, c in ((we, ce), (wi, ci)):
+        assert abs(w.sum() - 1.0) <= 1e-15 and abs(w @ c - 0.5) <= 1e-15
+    assert abs(we @ ci - 0.5) <= 1e-15 and abs(wi @ ce - 0.5) <= 1e-15
+    assert abs(kinetic.PR_DELTA - (1 - 1 / math.sqrt(2))) <= 1e-15  # the implicit diagonal gamma
+
+
+def velocity_transport(n, L, c):
+    # a transport stand-in that keeps the step local to the cell: T(y) = (c . v) y
+    V1, V2, V3, _ = grid(n, L)
+    w = c[0] * V1 + c[1] * V2 + c[2] * V3
+    return lambda y: w * y
+
+
+def test_pr222_conserves_the_transported_moments():
+    n, L = 24, 8.0
+    d, w = directions.icosa6()
+    plan = spectral.Plan(n, L, spectral.default_R(L), 1.0, 4.0, d, w)
+    f = kinetic.maxwellian(0.9, [0.2, -0.1, 0.0], 0.9, n, L) + kinetic.maxwellian(0.3, [-0.3, 0.2, 0.1], 1.1, n, L)
+    T = velocity_transport(n, L, [0.3, -0.2, 0.1])
+    dt, eps = 0.05, 0.1
+    out = kinetic.pr222_step(f, T, dt, eps, plan)
+    # rebuild the two stage values to know what the transport removed
+    g = kinetic.PR_DELTA
+    Y1 = kinetic.penalty_solve(f, g * dt, eps, L)
+    q1 = spectral.project(spectral.collide(Y1, plan), n, L)
+    R2 = f + dt * (-T(Y1) + (q1 - kinetic.penalty(Y1, L)) / eps) + dt * kinetic.PR_A_IMP[1, 0] * kinetic.penalty(Y1, L) / eps
+    Y2 = kinetic.penalty_solve(R2, g * dt, eps, L)
+    U = kinetic.conserved(f, n, L) - 0.5 * dt * (kinetic.conserved(T(Y1), n, L) + kinetic.conserved(T(Y2), n, L))
+    assert np.abs(kinetic.conserved(out, n, L) - U).max() <= 1e-11 * np.abs(U).max()
+
+
+def test_pr222_is_second_order_in_time():
+    # homogeneous relaxation y' = Q(y)/eps: error against a fine RK4 solution drops ~4x per halving of dt
+    n, L = 16, 8.0
+    d, w = directions.icosa6()
+    plan = spectral.Plan(n, L, spectral.default_R(L), 1.0, 4.0, d, w)
+    f = gen.bimaxwellian_batch(1, n, L, seed=2)[0]
+    eps, t_end = 5.0, 0.2  # beta dt / eps <= 0.13: the asymptotic (non-stiff) regime
+    zero = lambda y: np.zeros_like(y)
+
+    def Q(y):
+        return spectral.project(spectral.collide(y, plan), n, L) / eps
+
+    ref = f.copy()
+    h = t_end / 64
+    for _ in range(64):
+        k1 = Q(ref); k2 = Q(ref + 0.5 * h * k1); k3 = Q(ref + 0.5 * h * k2); k4 = Q(ref + h * k3)
+        ref = ref + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    errs = []
+    for steps in (4, 8, 16):
+        y = f.copy()
+        for _ in range(steps):
+            y = kinetic.pr222_step(y, zero, t_end / steps, eps, plan)
+        errs.append(np.linalg.norm(y - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 <= r1 <= 5.0 and 3.5 <= r2 <= 5.0, errs
