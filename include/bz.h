@@ -250,6 +250,38 @@ bz_status bz_imex_euler(const bz_plan* plan, const bz_imex_desc* desc, const dou
                         int32_t flags, void* stream);
 
 /*
+ * The same penalised splitting integrated in time with the second-order
+ * PR(2,2,2) IMEX Runge-Kutta scheme (tableaux of Sec. 4.3, C = 1/sqrt 2,
+ * implicit diagonal gamma = 1 - 1/sqrt 2), explicit part
+ * -v.grad_x y + (Q(y) - P(y))/eps, implicit part P(y)/eps, P(y) = beta (M[y] - y),
+ * beta = 2 pi rho.  Each implicit stage Y = R + (h/eps) P(Y) is solved by
+ * S(R, h) = (eps R + h beta M[R]) / (eps + h beta) (P conserves the invariants).
+ * Since both tableaux share their weights, the step reduces to
+ *   stage 1:  Y1 = S(y, gamma dt)
+ *   [caller:  T1 = v . grad_x Y1]
+ *   stage 2:  R2 = y - dt T1 + (dt/eps) Q(Y1) - (2 gamma dt/eps) P(Y1),
+ *             Y2 = S(R2, gamma dt),  A = y - (dt/2) T1 + (dt/(2 eps)) Q(Y1)
+ *   [caller:  T2 = v . grad_x Y2]
+ *   finish:   y_out = A - (dt/2) T2 + (dt/(2 eps)) Q(Y2)
+ * The transport terms need neighbouring cells, which is why the step is split
+ * where the caller evaluates them.  Q is the plan's operator (FP64 projected
+ * when the plan projects; an FP32 plan must project).
+ * Every array is device FP64 [*][n][n][n] and cell c lives at row idx[c] (idx
+ * NULL: row c) in all of them, inputs and outputs alike (the caller holds the
+ * stage values on its grid).  desc: dt > 0; eps or eps_cells (per row) > 0.
+ * Outputs must not alias the inputs of the same call (y_out may be y, which
+ * finish does not read).  Asynchronous on `stream`.
+ */
+bz_status bz_pr222_stage1(const bz_plan* plan, const bz_imex_desc* desc, const double* y, const int32_t* idx,
+                          int32_t ncells, const int32_t* ncells_dev, double* y1, void* stream);
+bz_status bz_pr222_stage2(const bz_plan* plan, const bz_imex_desc* desc, const double* y, const double* y1,
+                          const double* t1, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                          double* y2, double* a, void* stream);
+bz_status bz_pr222_finish(const bz_plan* plan, const bz_imex_desc* desc, const double* a, const double* y2,
+                          const double* t2, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                          double* y_out, void* stream);
+
+/*
  * ES-BGK operator of the intermediate layer (Sec. 2.2) and its first-order
  * IMEX step (Sec. 4.3, after Filbet and Jin), FP64, one cell per workgroup:
  *   rho Theta = int (v-u)(x)(v-u) f,  T = tr(Theta)/3,

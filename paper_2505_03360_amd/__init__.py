@@ -136,6 +136,9 @@ SIGNATURES = [
     ("bz_cell_moments", _I32, [_I32, ctypes.c_double, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(BzMomentsOut),
                                _I32, _VP]),
     ("bz_imex_euler", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_pr222_stage1", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _I32, _VP, _VP, _VP]),
+    ("bz_pr222_stage2", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP]),
+    ("bz_pr222_finish", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP]),
     ("bz_esbgk_collide", _I32, [ctypes.POINTER(BzEsbgkDesc), _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_esbgk_imex_euler", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32,
                                    _VP, _VP, _I32, _VP]),
@@ -279,6 +282,21 @@ def bz_imex_euler(plan: int, desc: BzImexDesc, f: int, tr: int, idx: int, ncells
     _check(lib().bz_imex_euler(plan, ctypes.byref(desc), f, tr, idx, ncells, ncells_dev, f_out, flags, stream))
 
 
+def bz_pr222_stage1(plan: int, desc: BzImexDesc, y: int, idx: int, ncells: int, ncells_dev: int, y1: int,
+                    stream: int = 0) -> None:
+    _check(lib().bz_pr222_stage1(plan, ctypes.byref(desc), y, idx, ncells, ncells_dev, y1, stream))
+
+
+def bz_pr222_stage2(plan: int, desc: BzImexDesc, y: int, y1: int, t1: int, idx: int, ncells: int,
+                    ncells_dev: int, y2: int, a: int, stream: int = 0) -> None:
+    _check(lib().bz_pr222_stage2(plan, ctypes.byref(desc), y, y1, t1, idx, ncells, ncells_dev, y2, a, stream))
+
+
+def bz_pr222_finish(plan: int, desc: BzImexDesc, a: int, y2: int, t2: int, idx: int, ncells: int,
+                    ncells_dev: int, y_out: int, stream: int = 0) -> None:
+    _check(lib().bz_pr222_finish(plan, ctypes.byref(desc), a, y2, t2, idx, ncells, ncells_dev, y_out, stream))
+
+
 def bz_esbgk_collide(desc: BzEsbgkDesc, f: int, idx: int, ncells: int, ncells_dev: int, q: int,
                      flags: int = 0, stream: int = 0) -> None:
     _check(lib().bz_esbgk_collide(ctypes.byref(desc), f, idx, ncells, ncells_dev, q, flags, stream))
@@ -414,6 +432,26 @@ class Collider:
         d = BzImexDesc(dt, eps, _ptr(eps_cells))
         bz_imex_euler(self.plan, d, _ptr(f), _ptr(tr), _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
                       BZ_SCATTER if scatter else 0, _stream(stream))
+        return out
+
+    def pr222_step(self, y, transport, dt: float, eps: float = 0.0, eps_cells=None, idx=None, out=None,
+                   stream=None):
+        """One PR(2,2,2) step through bz_pr222_stage1/stage2/finish; `transport`
+        maps a stage value (a tensor shaped like y) to v . grad_x of it and runs
+        between the calls.  Stage buffers are allocated like y."""
+        torch = _torch()
+        if y.dtype != torch.float64 or not y.is_contiguous() or not y.is_cuda:
+            raise ValueError("y must be a contiguous CUDA float64 tensor")
+        ncells = idx.numel() if idx is not None else y.numel() // self.n ** 3
+        d = BzImexDesc(dt, eps, _ptr(eps_cells))
+        st = _stream(stream)
+        y1, y2, a = torch.empty_like(y), torch.empty_like(y), torch.empty_like(y)
+        out = torch.empty_like(y) if out is None else out
+        bz_pr222_stage1(self.plan, d, _ptr(y), _ptr(idx), ncells, 0, _ptr(y1), st)
+        t1 = transport(y1).contiguous()
+        bz_pr222_stage2(self.plan, d, _ptr(y), _ptr(y1), _ptr(t1), _ptr(idx), ncells, 0, _ptr(y2), _ptr(a), st)
+        t2 = transport(y2).contiguous()
+        bz_pr222_finish(self.plan, d, _ptr(a), _ptr(y2), _ptr(t2), _ptr(idx), ncells, 0, _ptr(out), st)
         return out
 
     def close(self):

@@ -270,11 +270,137 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   }
 }
 
+struct PrArgs {
+  int ncells;
+  const int32_t* ncells_dev;
+  const int32_t* idx;
+  const double* eps_cells;
+  double eps, dt, h, dv;
+  const double* y;   // y^n
+  const double* y1;  // stage 1 value
+  const double* t1;  // transport of the stage value
+  double* a;         // in: Q(Y1); out: y - dt/2 T1 + dt/(2 eps) Q(Y1)
+  double* out;       // penalty solve: in R, out S(R); stage 2: Y2; finish: in Q(Y2), out y^{n+1}
+};
+
+// S(R, h) = (eps R + h beta M[R]) / (eps + h beta), beta = 2 pi rho(R): the
+// solution of the implicit stage Y = R + (h/eps) beta (M[Y] - Y) (the penalty
+// conserves the invariants, so M[Y] = M[R]).
+template <int N, int MODE>  // MODE 1: stage 2 (forms R2 and A first, then solves in place); 2: solve y into out
+__global__ __launch_bounds__(kThreads) void k_penalty(PrArgs a) {
+  constexpr int N3 = N * N * N;
+  __shared__ double red[5 * kWaves];
+  const int c = blockIdx.x;
+  if (c >= live_cells(a.ncells, a.ncells_dev)) return;
+  const int t = threadIdx.x;
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+  const size_t base = size_t(row) * N3;
+  const double eps = a.eps_cells ? a.eps_cells[row] : a.eps;
+  double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  [[maybe_unused]] double p1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // Maxwellian of Y1: cm, u, 1/2T, beta
+  if constexpr (MODE == 1) {
+    for (int j = t; j < N3; j += kThreads) {
+      const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
+      const double y1 = a.y1[base + j];
+      m[0] += y1;
+      m[1] += v1 * y1;
+      m[2] += v2 * y1;
+      m[3] += v3 * y1;
+      m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * y1;
+    }
+    block_sum<5>(m, red);
+    const double rho1 = a.dv * a.dv * a.dv * m[0];
+    p1[1] = m[1] / m[0];
+    p1[2] = m[2] / m[0];
+    p1[3] = m[3] / m[0];
+    const double T1 = (m[4] / m[0] - (p1[1] * p1[1] + p1[2] * p1[2] + p1[3] * p1[3])) / 3.0;
+    p1[0] = rho1 / ((2.0 * M_PI * T1) * sqrt(2.0 * M_PI * T1));
+    p1[4] = 1.0 / (2.0 * T1);
+    p1[5] = 2.0 * M_PI * rho1;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) m[k] = 0.0;
+  }
+  for (int j = t; j < N3; j += kThreads) {
+    const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
+    double r;
+    if constexpr (MODE == 1) {
+      // P(Y1) = beta1 (M[Y1] - Y1) from Y1's own moments;
+      // R2 = y - dt T1 + (dt/eps) Q(Y1) - (2 gamma dt/eps) P(Y1)   (the tableau's stage 2)
+      // A  = y - dt/2 T1 + dt/(2 eps) Q(Y1)                         (P cancels in the weights)
+      const double y = a.y[base + j], y1 = a.y1[base + j], t1 = a.t1[base + j], q1 = a.a[base + j];
+      const double d1 = v1 - p1[1], d2 = v2 - p1[2], d3 = v3 - p1[3];
+      const double g1 = p1[5] * (p1[0] * exp(-(d1 * d1 + d2 * d2 + d3 * d3) * p1[4]) - y1);
+      r = y - a.dt * t1 + (a.dt / eps) * q1 - (2.0 * a.h / eps) * g1;
+      a.a[base + j] = y - 0.5 * a.dt * t1 + (0.5 * a.dt / eps) * q1;
+      a.out[base + j] = r;
+    } else {
+      r = MODE == 2 ? a.y[base + j] : a.out[base + j];
+    }
+    m[0] += r;
+    m[1] += v1 * r;
+    m[2] += v2 * r;
+    m[3] += v3 * r;
+    m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * r;
+  }
+  block_sum<5>(m, red);  // also orders pass 1's writes before pass 2's reads
+  const double w = a.dv * a.dv * a.dv;
+  const double rho = w * m[0];
+  const double u1 = m[1] / m[0], u2 = m[2] / m[0], u3 = m[3] / m[0];
+  const double T = (m[4] / m[0] - (u1 * u1 + u2 * u2 + u3 * u3)) / 3.0;
+  const double cm = rho / ((2.0 * M_PI * T) * sqrt(2.0 * M_PI * T));
+  const double ia = 1.0 / (2.0 * T);
+  const double hb = a.h * 2.0 * M_PI * rho;
+  const double den = 1.0 / (eps + hb);
+  for (int j = t; j < N3; j += kThreads) {
+    const double d1 = node<N>(j / (N * N), a.dv) - u1, d2 = node<N>((j / N) % N, a.dv) - u2,
+                 d3 = node<N>(j % N, a.dv) - u3;
+    const double r = MODE == 2 ? a.y[base + j] : a.out[base + j];
+    a.out[base + j] = (eps * r + hb * cm * exp(-(d1 * d1 + d2 * d2 + d3 * d3) * ia)) * den;
+  }
+}
+
+// y^{n+1} = A - dt/2 T2 + dt/(2 eps) Q(Y2), Q(Y2) in `out` on entry.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_pr_finish(PrArgs a) {
+  constexpr int N3 = N * N * N;
+  const int c = blockIdx.x;
+  if (c >= live_cells(a.ncells, a.ncells_dev)) return;
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+  const size_t base = size_t(row) * N3;
+  const double eps = a.eps_cells ? a.eps_cells[row] : a.eps;
+  for (int j = threadIdx.x; j < N3; j += kThreads)
+    a.out[base + j] = a.a[base + j] - 0.5 * a.dt * a.t1[base + j] + (0.5 * a.dt / eps) * a.out[base + j];
+}
+
+// PR(2,2,2) kernels: 1 = stage-2 combination and solve, 2 = penalty solve of
+// `y` into `out`, 3 = finish.
+bz_status launch_pr(int kind, int n, int ncells, const PrArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(ncells)), block(kThreads);
+#define BZ_PR_CASE(NN)                                                                \
+  case NN:                                                                            \
+    if (kind == 1) hipLaunchKernelGGL((k_penalty<NN, 1>), grid, block, 0, s, a);      \
+    else if (kind == 2) hipLaunchKernelGGL((k_penalty<NN, 2>), grid, block, 0, s, a); \
+    else hipLaunchKernelGGL((k_pr_finish<NN>), grid, block, 0, s, a);                 \
+    break;
+  switch (n) {
+    BZ_PR_CASE(16)
+    BZ_PR_CASE(24)
+    BZ_PR_CASE(32)
+    BZ_PR_CASE(48)
+    default: return bz::fail(BZ_ERR_UNSUPPORTED, "pr222: n=%d", n);
+  }
+#undef BZ_PR_CASE
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "pr222: launch failed: %s", hipGetErrorString(e));
+  return BZ_OK;
+}
+
 }  // namespace
 
 namespace bz {
 
 bool kinetic_n_supported(int n) { return n == 16 || n == 24 || n == 32 || n == 48; }
+
 
 bz_status launch_imex_params(int n, double dv, const int32_t* idx, int ncells, const int32_t* ncells_dev,
                              const double* f, const double* tr, double dt, double* par, hipStream_t s) {
@@ -412,4 +538,101 @@ extern "C" bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* d, const bz_imex_d
   a.dv = 2.0 * d->L / d->n;
   a.out = f_out;
   return esbgk_launch<true>(d, a, ncells, stream, "bz_esbgk_imex_euler");
+}
+
+// ---------------------------------------------------------------- PR(2,2,2) entry points
+namespace {
+
+constexpr double kPrGamma = 0.29289321881345248;  // 1 - 1/sqrt(2), the implicit diagonal
+
+bz_status pr_check(const char* who, const bz_plan* p, const bz_imex_desc* d, int32_t ncells) {
+  if (!p) return bz::fail(BZ_ERR_ARG, "%s: null plan", who);
+  if (!d) return bz::fail(BZ_ERR_ARG, "%s: null descriptor", who);
+  if (!p->ws_dev) return bz::fail(BZ_ERR_STATE, "%s: plan not bound", who);
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return bz::fail(BZ_ERR_ARG, "%s: dt must be > 0", who);
+  if (!d->eps_cells && !(d->eps > 0.0)) return bz::fail(BZ_ERR_ARG, "%s: eps must be > 0", who);
+  if (ncells < 0) return bz::fail(BZ_ERR_ARG, "%s: ncells < 0", who);
+  if (!p->project && p->fp32) return bz::fail(BZ_ERR_UNSUPPORTED, "%s: an FP32 plan must project (FP64 output)", who);
+  if (ncells > p->capacity)
+    return bz::fail(BZ_ERR_NOMEM, "%s: %d cells exceed the bound capacity %d", who, ncells, p->capacity);
+  return BZ_OK;
+}
+
+PrArgs pr_args(const bz_plan* p, const bz_imex_desc* d, const int32_t* idx, int ncells, const int32_t* ncells_dev) {
+  PrArgs a{};
+  a.ncells = ncells;
+  a.ncells_dev = ncells_dev;
+  a.idx = idx;
+  a.eps_cells = d->eps_cells;
+  a.eps = d->eps;
+  a.dt = d->dt;
+  a.h = kPrGamma * d->dt;
+  a.dv = p->dv;
+  return a;
+}
+
+bz_status pr_collide(const bz_plan* p, const double* f, const int32_t* idx, int ncells, const int32_t* ncells_dev,
+                     double* q, hipStream_t s) {
+  bz::Binding b;
+  b.tables = p->tables_dev;
+  b.ws = p->ws_dev;
+  b.capacity = p->capacity;
+  b.lay = p->ws;
+  return bz::launch_collide(p, b, f, 0, idx, ncells, ncells_dev, q, 1, s, p->timing);
+}
+
+}  // namespace
+
+extern "C" bz_status bz_pr222_stage1(const bz_plan* p, const bz_imex_desc* d, const double* y, const int32_t* idx,
+                                     int32_t ncells, const int32_t* ncells_dev, double* y1, void* stream) {
+  bz::clear_error();
+  bz_status st = pr_check("bz_pr222_stage1", p, d, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!y || !y1) return bz::fail(BZ_ERR_ARG, "bz_pr222_stage1: null y or y1");
+  if (y1 == y) return bz::fail(BZ_ERR_ARG, "bz_pr222_stage1: y1 must not alias y");
+  PrArgs a = pr_args(p, d, idx, ncells, ncells_dev);
+  a.y = y;
+  a.out = y1;
+  return launch_pr(2, p->n, ncells, a, static_cast<hipStream_t>(stream));
+}
+
+extern "C" bz_status bz_pr222_stage2(const bz_plan* p, const bz_imex_desc* d, const double* y, const double* y1,
+                                     const double* t1, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                                     double* y2, double* a_out, void* stream) {
+  bz::clear_error();
+  bz_status st = pr_check("bz_pr222_stage2", p, d, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!y || !y1 || !t1 || !y2 || !a_out) return bz::fail(BZ_ERR_ARG, "bz_pr222_stage2: null array");
+  const void* in[3] = {y, y1, t1};
+  for (const void* q : in)
+    if (q == y2 || q == a_out) return bz::fail(BZ_ERR_ARG, "bz_pr222_stage2: outputs must not alias inputs");
+  if (y2 == a_out) return bz::fail(BZ_ERR_ARG, "bz_pr222_stage2: y2 and a must differ");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = pr_collide(p, y1, idx, ncells, ncells_dev, a_out, s);  // Q(Y1) into A's rows
+  if (st != BZ_OK) return st;
+  PrArgs a = pr_args(p, d, idx, ncells, ncells_dev);
+  a.y = y;
+  a.y1 = y1;
+  a.t1 = t1;
+  a.a = a_out;
+  a.out = y2;
+  return launch_pr(1, p->n, ncells, a, s);
+}
+
+extern "C" bz_status bz_pr222_finish(const bz_plan* p, const bz_imex_desc* d, const double* a_in, const double* y2,
+                                     const double* t2, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                                     double* y_out, void* stream) {
+  bz::clear_error();
+  bz_status st = pr_check("bz_pr222_finish", p, d, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!a_in || !y2 || !t2 || !y_out) return bz::fail(BZ_ERR_ARG, "bz_pr222_finish: null array");
+  if (y_out == a_in || y_out == y2 || y_out == t2) return bz::fail(BZ_ERR_ARG, "bz_pr222_finish: y_out must not alias inputs");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = pr_collide(p, y2, idx, ncells, ncells_dev, y_out, s);  // Q(Y2) into y_out's rows
+  if (st != BZ_OK) return st;
+  PrArgs a = pr_args(p, d, idx, ncells, ncells_dev);
+  a.a = const_cast<double*>(a_in);
+  a.t1 = t2;
+  a.out = y_out;
+  return launch_pr(3, p->n, ncells, a, s);
 }

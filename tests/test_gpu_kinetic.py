@@ -183,3 +183,34 @@ def test_esbgk_imex_against_oracle(n):
         ref = kinetic.esbgk_imex_euler(f[r], tr[r], dt, 0.05, L, beta, mu0)
         assert np.linalg.norm(got[r] - ref) <= 1e-12 * np.linalg.norm(ref)
     assert np.array_equal(got[1], f[1])
+
+
+@pytest.mark.parametrize("n,rule,m,prec", [(16, "icosa6", 6, "fp64"), (16, "icosa6", 6, "fp32"),
+                                           (32, "spiral", 32, "fp32"), (24, "spiral", 32, "fp32")])
+def test_pr222_against_oracle(n, rule, m, prec):
+    import paper_2505_03360_amd as bz
+    print("case pr222", n, rule, m, prec, flush=True)
+    L, dt, eps = 8.0, 0.01, 0.05
+    f = gen.shock_batch(4, n, L, seed=60 + n)
+    rows = [3, 1]
+    v = spectral.velocity_nodes(n, L)
+    V1, V2, V3 = np.meshgrid(v, v, v, indexing="ij")
+    wv = 0.4 * V1 - 0.3 * V2 + 0.2 * V3  # T(y) = (c . v) y keeps the step cell-local
+    plan = oracle_plan(n, rule=rule, m=m)
+    ref = [kinetic.pr222_step(f[r], lambda z: wv * z, dt, eps, plan) for r in rows]
+    q_ref, loss_ref = oracle_cells(f[rows], plan)
+    col = bz.Collider(n, len(rows), L=L, precision=bz.BZ_FP32 if prec == "fp32" else bz.BZ_FP64,
+                      **lib_kwargs(rule, m))
+    ft = torch.from_numpy(f).cuda()
+    wt = torch.from_numpy(wv).cuda()
+    idx = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    out = col.pr222_step(ft, lambda z: z * wt, dt, eps=eps, idx=idx).cpu().numpy()
+    tol_q = 1e-5 if prec == "fp32" else 1e-12
+    for c, r in enumerate(rows):
+        qn = max(np.linalg.norm(q_ref[c]), 0.05 * np.linalg.norm(loss_ref[c]))
+        err = np.linalg.norm(out[r] - ref[c])
+        # two evaluations of Q enter y^{n+1} with weight dt/(2 eps), and one more through Y2
+        bound = 4 * tol_q * (dt / eps) * qn + 1e-13 * np.linalg.norm(ref[c])
+        print(f"  row {r}: err {err:.3e} bound {bound:.3e}", flush=True)
+        assert err <= bound
+    col.close()

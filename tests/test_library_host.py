@@ -147,3 +147,14 @@ def test_esbgk_validation():
         bz.bz_esbgk_collide(good, 0, 0, 4, 0, 0)  # null pointers
     assert e.value.code == bz.BZ_ERR_ARG
     bz.bz_esbgk_collide(good, 0, 0, 0, 0, 0)  # empty batch
+
+
+def test_pr222_validation():
+    p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=6, precision=bz.BZ_FP64))
+    d = bz.BzImexDesc(0.01, 0.1, None)
+    for fn, args in ((bz.bz_pr222_stage1, (0, 0, 1, 0, 0)), (bz.bz_pr222_stage2, (0, 0, 0, 0, 1, 0, 0, 0)),
+                     (bz.bz_pr222_finish, (0, 0, 0, 0, 1, 0, 0))):
+        with pytest.raises(bz.BzError) as e:
+            fn(p, d, *args)
+        assert e.value.code == bz.BZ_ERR_STATE  # not bound
+    bz.bz_plan_destroy(p)
