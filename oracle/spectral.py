@@ -218,6 +218,29 @@ def collide(f: np.ndarray, plan: Plan) -> np.ndarray:
     return collide_parts(f, plan)[0]
 
 
+def collide_fft(f: np.ndarray, plan: Plan) -> np.ndarray:
+    """The same operator with library FFTs for the transforms (the paper's CPU
+    evaluation: an FFT per cell and direction).  On the grid v_j = (j - N/2) dv
+    the exact transforms are the standard DFT times the phase (-1)^ktilde,
+    which cancels between every forward/inverse pair, so
+        A_p = N^3 IDFT(alpha_p DFT(f)/N^3), etc.
+    Used to time a CPU evaluation whose cost scales like the method's; pinned
+    to collide() in the tests."""
+    n = plan.n
+    fh = np.fft.fftn(f) / float(n) ** 3
+    fh[nyquist_mask(n)] = 0.0
+
+    def inv(g):
+        return np.fft.ifftn(g).real * float(n) ** 3
+
+    qplus = np.zeros((n, n, n))
+    for p in range(plan.m):
+        a, ap = multipliers(plan, p)
+        qplus += plan.weights[p] * inv(a * fh) * inv(ap * fh)
+    loss = inv(fh) * inv(bhat_m(plan) * fh)
+    return plan.kernel_c * (qplus - loss)
+
+
 def moment_matrix(n: int, L: float) -> np.ndarray:
     """C (5 x n^3): rows 1, v1, v2, v3, |v|^2 at the grid points (the
     collision invariants of hypothesis (H1); the common factor dv^3 cancels)."""

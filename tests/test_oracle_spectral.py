@@ -275,3 +275,14 @@ def test_rel_err_floor():
     assert spectral.rel_err(q * (1 + 1e-6), q) == pytest.approx(1e-6, rel=1e-6)
     small = q * 1e-6
     assert spectral.rel_err(small + 1e-3, small, loss_ref=q) == pytest.approx(1e-3 / 0.05, rel=1e-9)
+
+
+def test_fft_mode_equals_the_naive_dft_oracle():
+    # the library-FFT evaluation is the same discrete operator (phases cancel in pairs)
+    import bz_inputs as gen
+    from oracle import directions
+    for n, rule in ((16, directions.icosa6()), (24, directions.spiral(32))):
+        plan = spectral.Plan(n, 8.0, spectral.default_R(8.0), 1.0, 4.0, *rule)
+        f = gen.shock_batch(1, n, 8.0, seed=3)[0]
+        q = spectral.collide(f, plan)
+        assert np.abs(spectral.collide_fft(f, plan) - q).max() <= 1e-12 * np.abs(q).max()
