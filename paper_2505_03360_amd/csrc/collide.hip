@@ -60,6 +60,7 @@ struct PlainArgs {
   int pass;
   int first;
   int loss;  // this pass is the loss pass (the last one)
+  int m1;    // passes (directions + the loss pass)
 };
 
 // ------------------------------------------------------------------ forward
@@ -204,6 +205,111 @@ __global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
 #pragma unroll
     for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] += wp * x[j1].x * x[j1].y;
   }
+}
+
+// ------------------------------------------------------------------ chunked plain passes (FP32)
+// Two kernels per chunk of directions, for the sizes and strategies without a
+// fused kernel:
+//   k_pA:  thread (cell, k2, k1) loads its fhat pencil along k3 once and, for
+//          each direction d of the chunk, writes the inverse along k3 of
+//          M_p fhat to y[cell][d][j3][k2][k1] (planes of fixed j3 contiguous);
+//   k_pBC: one wave per 64/N planes of fixed j3: pencils along k2 read from
+//          y, inverse, transpose through LDS inside the workgroup, inverse along
+//          k1, products accumulated in registers over the chunk, accumulator
+//          kept plane-major acc[cell][j3][j1][j2].
+// Per cell and direction this moves fhat/K + y twice + acc twice/K (K the
+// chunk) instead of fhat + y four times + acc twice.
+constexpr int kPlainChunk = 2;
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (N * N));
+  const int rem = int(g % (N * N));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int k2 = rem / N, k1 = rem % N;
+  const size_t off = size_t(k2) * N * N + k1;
+  const cx<T>* fh = a.fh + c * a.fh_stride + off;
+  cx<T> F[N];
+#pragma unroll
+  for (int k3 = 0; k3 < N; ++k3) F[k3] = fh[size_t(k3) * N];
+  for (int d = 0; d < kPlainChunk; ++d) {
+    const int p = a.pass + d;
+    if (p >= a.m1) break;
+    const cx<T>* mu = a.mult + size_t(p) * N * N * N + off;
+    cx<T> x[N];
+#pragma unroll
+    for (int k3 = 0; k3 < N; ++k3) {
+      const cx<T> M = mu[size_t(k3) * N];
+      x[k3] = {M.x * F[k3].x - M.y * F[k3].y, M.x * F[k3].y + M.y * F[k3].x};
+    }
+    bzk::fft<N, 1>(x);
+    cx<T>* y = a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(k2) * N + k1;
+#pragma unroll
+    for (int j3 = 0; j3 < N; ++j3) y[size_t(j3) * N * N] = x[j3];
+  }
+}
+
+template <int N>
+constexpr int plain_planes_per_wave() { return 64 / N; }
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_pBC(PlainArgs<T> a) {
+  constexpr int PL = plain_planes_per_wave<N>();  // planes per wave
+  constexpr int PW = 4 * PL;                      // planes per workgroup
+  constexpr int NG = N / PW;                      // workgroups per cell
+  static_assert(N % PW == 0, "planes must tile the cell");
+  __shared__ cx<T> tr[PW][N][N + 1];  // [plane][j2][k1], odd pitch
+  const int c = blockIdx.x / NG, grp = blockIdx.x % NG;
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int t = threadIdx.x, wv = t / 64, lane = t % 64;
+  const bool act = lane < PL * N;
+  const int pl = wv * PL + (act ? lane / N : 0);
+  const int k = lane % N;  // stage B: k1; stage C: j2
+  const int j3 = grp * PW + pl;
+  T* acc = a.acc + c * a.acc_stride + size_t(j3) * N * N;  // [j1][j2] of plane j3
+  T accr[N];
+#pragma unroll
+  for (int j1 = 0; j1 < N; ++j1) accr[j1] = (act && !a.first) ? acc[size_t(j1) * N + k] : T(0);
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+  for (int d = 0; d < kPlainChunk; ++d) {
+    const int p = a.pass + d;
+    if (p >= a.m1) break;
+    const T wp = a.w[p];
+    if (act) {
+      const cx<T>* y = a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(j3) * N * N + k;
+      cx<T> x[N];
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) x[k2] = y[size_t(k2) * N];
+      bzk::fft<N, 1>(x);
+#pragma unroll
+      for (int j2 = 0; j2 < N; ++j2) tr[pl][j2][k] = x[j2];
+    }
+    __syncthreads();
+    if (act) {
+      cx<T> x[N];
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const int k1 = bzk::first_stage_order<N>(r);
+        x[k1] = tr[pl][k][k1];
+      }
+      bzk::fft<N, 1>(x);
+      if (p == a.m1 - 1) {
+        // loss pass: acc -= (sL f - Im) Re with the exact input f at (j1, j2 = k, j3)
+        const size_t fb = size_t(row) * N * N * N + size_t(k) * N + j3;
+#pragma unroll
+        for (int j1 = 0; j1 < N; ++j1)
+          accr[j1] -= (wp * load_f<T>(a.f, a.f_fp32, fb + size_t(j1) * N * N) - x[j1].y) * x[j1].x;
+      } else {
+#pragma unroll
+        for (int j1 = 0; j1 < N; ++j1) accr[j1] += wp * x[j1].x * x[j1].y;
+      }
+    }
+    __syncthreads();  // tr is rewritten by the next direction
+  }
+  if (act)
+#pragma unroll
+    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N + k] = accr[j1];
 }
 
 // ------------------------------------------------------------------ fused FP32
@@ -763,6 +869,81 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   }
 }
 
+// Projection of a plane-major accumulator acc[cell][j3][j1][j2] (one chunk,
+// FP32, from the chunked plain passes).  Moments are summed in the
+// accumulator's own order (fixed); the output [j1][j2][j3] is written through
+// LDS tiles of 32 (j1, j2) columns so that both the reads and the writes are
+// coalesced.
+__global__ __launch_bounds__(256) void k_project_pm(ProjArgs a) {
+  const int c = blockIdx.x;
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int n = a.n;
+  const size_t n2 = size_t(n) * n, n3 = n2 * n;
+  const float* acc = static_cast<const float*>(a.acc) + size_t(c) * a.acc_stride;
+  const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
+  const size_t frow = a.idx ? size_t(a.idx[c]) : size_t(c);
+  const int t = threadIdx.x;
+  __shared__ double red[5][256];
+  __shared__ double tile[48][33];  // [j3][column], n <= 48
+  double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (a.project) {
+    double m[5] = {0, 0, 0, 0, 0};
+    for (size_t e = t; e < n3; e += blockDim.x) {
+      const int j3 = int(e / n2), j1 = int((e / n) % n), j2 = int(e % n);
+      const double v1 = (j1 - n / 2) * a.dv, v2 = (j2 - n / 2) * a.dv, v3 = (j3 - n / 2) * a.dv;
+      const double qv = a.C * double(acc[e]);
+      m[0] += qv;
+      m[1] += v1 * qv;
+      m[2] += v2 * qv;
+      m[3] += v3 * qv;
+      m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k][t] = m[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (t < h)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + h];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      double x = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) x += a.ginv[5 * i + k] * red[k][0];
+      lam[i] = x;
+    }
+  }
+  const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
+  for (size_t J0 = 0; J0 < n2; J0 += 32) {
+    __syncthreads();  // the previous tile has been written out
+    for (int i = t; i < n * 32; i += blockDim.x) {
+      const int j3 = i / 32, jj = i % 32;
+      tile[j3][jj] = a.C * double(acc[size_t(j3) * n2 + J0 + jj]);
+    }
+    __syncthreads();
+    for (int i = t; i < 32 * n; i += blockDim.x) {
+      const int jj = i / n, j3 = i % n;
+      const size_t J = J0 + jj;
+      const int j1 = int(J / n), j2 = int(J % n);
+      const size_t j = J * n + j3;  // [j1][j2][j3]
+      const double v1 = (j1 - n / 2) * a.dv, v2 = (j2 - n / 2) * a.dv, v3 = (j3 - n / 2) * a.dv;
+      double qv = tile[j3][jj];
+      if (a.project) qv -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
+      if (a.imex) {
+        const size_t fe = frow * n3 + j;
+        static_cast<double*>(a.q)[row * n3 + j] = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe],
+                                                                  a.im.tr[fe], eps_c, a.im.dt, v1, v2, v3);
+      } else if (a.project || !a.q_fp32) {
+        static_cast<double*>(a.q)[row * n3 + j] = qv;
+      } else {
+        static_cast<float*>(a.q)[row * n3 + j] = float(qv);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T, int N>
 void launch_plain_forward(const PlainArgs<T>& a, int ncells, hipStream_t s) {
@@ -777,6 +958,18 @@ template <typename T, int N>
 void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   const long threads = long(ncells) * N * N;
   const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+  a.m1 = m1;
+  if constexpr (sizeof(T) == 4) {
+    constexpr int NG = N / (4 * plain_planes_per_wave<N>());
+    const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
+    for (int p0 = 0; p0 < m1; p0 += kPlainChunk) {
+      a.pass = p0;
+      a.first = p0 == 0;
+      hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_pBC<T, N>), grid_bc, block_bc, 0, s, a);
+    }
+    return;
+  }
   for (int p = 0; p < m1; ++p) {
     a.pass = p;
     a.first = p == 0;
@@ -952,7 +1145,12 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   }
   if (st != BZ_OK) return st;
   if (timed) (void)hipEventRecord(pm->ev[2], s);
-  if (!fused_projection) hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  if (!fused_projection) {
+    if (p->fp32 && p->transform == BZ_XF_PLAIN)
+      hipLaunchKernelGGL(k_project_pm, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+    else
+      hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  }
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);
     pm->timed_calls += 1;
