@@ -191,7 +191,7 @@ def serving_run(seconds: float, seed: int = 5):
                         "FP32 + FP64 projection, 16 GiB arena"}
 
 
-def sweep(cells: int = 1024, reps: int = 3):
+def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.0, 0.5, 1.0)):
     """Precision sweep: N in {32, 48}, M in {32, 64}, gamma in {0, 0.5, 1};
     FP32 (fused at N=32, plain passes at N=48) and FP64 plain on the same
     cells (64 seeded shock cells tiled to `cells`).  Reports time per batch,
@@ -205,7 +205,7 @@ def sweep(cells: int = 1024, reps: int = 3):
     import paper_2505_03360_amd as bz
 
     out = []
-    for n in (32, 48):
+    for n in ns:
         base = torch.from_numpy(gen.shock_batch(64, n, L, seed=4)).cuda()
         f = base.repeat(cells // 64, 1, 1, 1).contiguous()
         v = (torch.arange(n, dtype=torch.float64, device="cuda") - n // 2) * (2 * L / n)
@@ -217,8 +217,8 @@ def sweep(cells: int = 1024, reps: int = 3):
             num = (qq @ C.T).abs()
             den = qq.abs() @ C.abs().T
             return float((num / den).max())
-        for m in (32, 64):
-            for gamma in (0.0, 0.5, 1.0):
+        for m in ms:
+            for gamma in gammas:
                 rec = {"n": n, "m": m, "gamma": gamma, "cells": cells}
                 res = {}
                 for name, prec, proj in (("fp32", bz.BZ_FP32, 1), ("fp64", bz.BZ_FP64, 1), ("fp32_raw", bz.BZ_FP32, 0)):
@@ -311,6 +311,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run length (0 = skip)")
     ap.add_argument("--sweep", action="store_true", help="run the precision sweep instead (one JSON line per case)")
+    ap.add_argument("--sweep-n", type=int, nargs="*", default=[32, 48])
+    ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
+    ap.add_argument("--sweep-gamma", type=float, nargs="*", default=[0.0, 0.5, 1.0])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -327,7 +330,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.sweep:
-        sweep()
+        sweep(ns=args.sweep_n, ms=args.sweep_m, gammas=args.sweep_gamma)
         return
     f_np = gen.shock_batch(CELLS, N, L, seed=2)
     f = torch.from_numpy(f_np).cuda()
