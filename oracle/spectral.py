@@ -218,6 +218,48 @@ def collide(f: np.ndarray, plan: Plan) -> np.ndarray:
     return collide_parts(f, plan)[0]
 
 
+def padded_plan(plan: Plan) -> Plan:
+    """The same operator on the 3n/2 grid over the same box [-L, L)^3 (same
+    wavenumber spacing pi/L, same R, kernel and directions)."""
+    if (3 * plan.n) % 2:
+        raise ValueError("n must be even")
+    return Plan(3 * plan.n // 2, plan.L, plan.R, plan.gamma, plan.kernel_c, plan.dirs, plan.weights)
+
+
+def _band(n: int) -> np.ndarray:
+    """Indices (on an n-point wavenumber axis) of the modes |ktilde| < n/2."""
+    k = np.arange(n)
+    return np.where(k < n // 2, k, k - n)
+
+
+def collide_dealiased(f: np.ndarray, plan: Plan) -> np.ndarray:
+    """The truncated convolution without wrap-around: the sums over l + m = k
+    taken over the truncated series' own modes, as integers (the paper's
+    sums over l + m = k), for the output modes |ktilde| < n/2.  Evaluated by
+    the 3/2 rule: the truncated series of f sampled on the 3n/2 grid, the fast
+    operator there, and the result truncated back to the n modes (a product of
+    two series with |ktilde| < n/2 has modes |ktilde| < n, and on a 3n/2-point
+    axis the wrapped ones land outside |ktilde| < n/2)."""
+    n, L = plan.n, plan.L
+    pp = padded_plan(plan)
+    np_ = pp.n
+    fh = forward(f, n, L)  # Nyquist zeroed
+    kt = _band(n)
+    sel = np.abs(kt) < n // 2
+    ip = np.where(kt[sel] >= 0, kt[sel], kt[sel] + np_)  # the same modes on the padded axis
+    g = np.zeros((np_,) * 3, dtype=complex)
+    g[np.ix_(ip, ip, ip)] = fh[np.ix_(np.flatnonzero(sel), np.flatnonzero(sel), np.flatnonzero(sel))]
+    fp = inverse(g, np_, L)
+    assert np.abs(fp.imag).max() <= 1e-12 * np.abs(fp.real).max()
+    qp = collide(fp.real, pp)
+    qh = forward(qp, np_, L)
+    out = np.zeros((n,) * 3, dtype=complex)
+    out[np.ix_(np.flatnonzero(sel), np.flatnonzero(sel), np.flatnonzero(sel))] = qh[np.ix_(ip, ip, ip)]
+    q = inverse(out, n, L)
+    assert np.abs(q.imag).max() <= 1e-12 * np.abs(q.real).max()
+    return q.real
+
+
 def collide_fft(f: np.ndarray, plan: Plan) -> np.ndarray:
     """The same operator with library FFTs for the transforms (the paper's CPU
     evaluation: an FFT per cell and direction).  On the grid v_j = (j - N/2) dv
