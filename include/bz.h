@@ -97,6 +97,10 @@ typedef struct {
   int32_t chunks;        /* fused path: direction chunks per cell (0 = auto) */
   int32_t slices;        /* fused path: j3 slices of the LDS transposes, 1 or 2
                             (n = 16 only; n = 32 always uses 2); 0 = auto */
+  int32_t dealias;       /* 0: circular convolution (l + m = k mod n);
+                            1: truncated convolution without wrap-around
+                            (l + m = k over the series' own modes), evaluated
+                            by the 3/2 rule on a padded 3n/2 grid; n = 16, 32 */
 } bz_plan_desc;
 
 typedef struct bz_plan bz_plan;

@@ -232,14 +232,16 @@ def _band(n: int) -> np.ndarray:
     return np.where(k < n // 2, k, k - n)
 
 
-def collide_dealiased(f: np.ndarray, plan: Plan) -> np.ndarray:
+def collide_dealiased(f: np.ndarray, plan: Plan, op=None) -> np.ndarray:
     """The truncated convolution without wrap-around: the sums over l + m = k
     taken over the truncated series' own modes, as integers (the paper's
     sums over l + m = k), for the output modes |ktilde| < n/2.  Evaluated by
     the 3/2 rule: the truncated series of f sampled on the 3n/2 grid, the fast
     operator there, and the result truncated back to the n modes (a product of
     two series with |ktilde| < n/2 has modes |ktilde| < n, and on a 3n/2-point
-    axis the wrapped ones land outside |ktilde| < n/2)."""
+    axis the wrapped ones land outside |ktilde| < n/2).  `op` evaluates the
+    operator on the padded grid (default collide; collide_fft is the same
+    operator, pinned to it, and faster for large grids)."""
     n, L = plan.n, plan.L
     pp = padded_plan(plan)
     np_ = pp.n
@@ -251,7 +253,7 @@ def collide_dealiased(f: np.ndarray, plan: Plan) -> np.ndarray:
     g[np.ix_(ip, ip, ip)] = fh[np.ix_(np.flatnonzero(sel), np.flatnonzero(sel), np.flatnonzero(sel))]
     fp = inverse(g, np_, L)
     assert np.abs(fp.imag).max() <= 1e-12 * np.abs(fp.real).max()
-    qp = collide(fp.real, pp)
+    qp = (op or collide)(fp.real, pp)
     qh = forward(qp, np_, L)
     out = np.zeros((n,) * 3, dtype=complex)
     out[np.ix_(np.flatnonzero(sel), np.flatnonzero(sel), np.flatnonzero(sel))] = qh[np.ix_(ip, ip, ip)]

@@ -47,6 +47,7 @@ class BzPlanDesc(ctypes.Structure):
         ("max_cells", ctypes.c_int32),
         ("chunks", ctypes.c_int32),
         ("slices", ctypes.c_int32),
+        ("dealias", ctypes.c_int32),
     ]
 
 
@@ -189,12 +190,13 @@ def bz_last_error() -> str:
 def make_plan_desc(n: int, L: float = 8.0, R: float = 0.0, gamma: float = 1.0, kernel_c: float = 4.0,
                    m: int = 6, dir_kind: int = BZ_DIRS_ICOSA6, dirs=None, weights=None, a1: int = 0,
                    a2: int = 0, precision: int = BZ_FP32, transform: int = BZ_XF_AUTO, project: int = 1,
-                   max_cells: int = 1, chunks: int = 0, slices: int = 0) -> BzPlanDesc:
+                   max_cells: int = 1, chunks: int = 0, slices: int = 0, dealias: int = 0) -> BzPlanDesc:
     d = BzPlanDesc()
     d.n, d.L, d.R, d.gamma, d.kernel_c = n, L, R, gamma, kernel_c
     d.m, d.dir_kind, d.a1, d.a2 = m, dir_kind, a1, a2
     d.precision, d.transform, d.project, d.max_cells, d.chunks = precision, transform, project, max_cells, chunks
     d.slices = slices
+    d.dealias = dealias
     d._keep = []
     if dirs is not None:
         import numpy as np

@@ -23,6 +23,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct WsLayout {
   size_t fh_off, y_off, acc_off, par_off;  // byte offsets into ws_dev
   size_t fh_cell, y_cell, acc_cell, par_cell;  // bytes per cell of each region
+  // dealiased plans: padded f, padded raw Q, padded spectrum, the padded plan's workspace
+  size_t fp_off = 0, qp_off = 0, gp_off = 0, pad_off = 0;
+  size_t fp_cell = 0, qp_cell = 0, gp_cell = 0, pad_cell = 0;
 };
 
 // Device memory one evaluation runs on: the plan's uploaded tables and a
@@ -47,6 +50,7 @@ struct bz_plan {
   int transform = BZ_XF_PLAIN;  // resolved strategy
   int chunks = 1;               // direction chunks per cell (fused path)
   int slices = 2;               // j3 slices of the fused kernel's transposes
+  bz_plan* pad = nullptr;       // dealiased plans: the same operator on the 3n/2 grid (raw Q)
   std::vector<double> dirs;     // [m][3]
   std::vector<double> w;        // [m]
   // FP64 host tables in device layout [p][k2][k3][k1] x (a, a'), p < m1;

@@ -207,6 +207,64 @@ __global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------ spectral resampling
+// Inverse transform on an NO-point grid of a spectrum given on NI points
+// (fhat layout [k2][k3][k1]), keeping the modes |ktilde| < min(NI, NO)/2 and
+// zero elsewhere: the truncated series re-sampled on the other grid (the 3/2
+// rule of the dealiased plans).  Three pencil passes like the plain path:
+// k_rsA (along k3, with the mode map), k_dirB (along k2), k_rsC (along k1,
+// real part to a[cell][j1][j2][j3]).
+template <int NI, int NO>
+__device__ __forceinline__ int rs_map(int k) {  // NO-axis index -> NI-axis index, or -1 outside the band
+  constexpr int B = (NI < NO ? NI : NO) / 2;
+  const int kt = k < NO / 2 ? k : k - NO;
+  if (kt >= B || kt <= -B) return -1;
+  return kt >= 0 ? kt : kt + NI;
+}
+
+template <typename T, int NI, int NO>
+__global__ __launch_bounds__(256) void k_rsA(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (NO * NO));
+  const int rem = int(g % (NO * NO));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int k2 = rem / NO, k1 = rem % NO;
+  const int m2 = rs_map<NI, NO>(k2), m1 = rs_map<NI, NO>(k1);
+  cx<T> x[NO];
+  if (m1 >= 0 && m2 >= 0) {
+    const cx<T>* gin = a.fh + c * a.fh_stride + size_t(m2) * NI * NI + m1;
+#pragma unroll
+    for (int k3 = 0; k3 < NO; ++k3) {
+      const int m3 = rs_map<NI, NO>(k3);
+      x[k3] = m3 >= 0 ? gin[size_t(m3) * NI] : cx<T>{T(0), T(0)};
+    }
+    bzk::fft<NO, 1>(x);
+  } else {
+#pragma unroll
+    for (int j3 = 0; j3 < NO; ++j3) x[j3] = cx<T>{T(0), T(0)};
+  }
+  cx<T>* y = a.y + c * a.y_stride + size_t(k2) * NO * NO + k1;
+#pragma unroll
+  for (int j3 = 0; j3 < NO; ++j3) y[size_t(j3) * NO] = x[j3];
+}
+
+template <typename T, int NO>
+__global__ __launch_bounds__(256) void k_rsC(PlainArgs<T> a) {
+  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = int(g / (NO * NO));
+  const int rem = int(g % (NO * NO));
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int j2 = rem / NO, j3 = rem % NO;
+  const cx<T>* y = a.y + c * a.y_stride + size_t(j2) * NO * NO + size_t(j3) * NO;
+  cx<T> x[NO];
+#pragma unroll
+  for (int k1 = 0; k1 < NO; ++k1) x[k1] = y[k1];
+  bzk::fft<NO, 1>(x);
+  T* out = a.acc + c * a.acc_stride + size_t(j2) * NO + j3;
+#pragma unroll
+  for (int j1 = 0; j1 < NO; ++j1) out[size_t(j1) * NO * NO] = x[j1].x;
+}
+
 // ------------------------------------------------------------------ chunked plain passes (FP32)
 // Two kernels per chunk of directions, for the sizes and strategies without a
 // fused kernel:
@@ -1024,6 +1082,99 @@ void launch_fused(const FusedArgs& a, int ncells, hipStream_t s) {
 
 }  // namespace
 
+template <typename T, int NI, int NO>
+void launch_resample(PlainArgs<T> a, int ncells, hipStream_t s) {
+  const long threads = long(ncells) * NO * NO;
+  const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+  hipLaunchKernelGGL((k_rsA<T, NI, NO>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((k_dirB<T, NO>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((k_rsC<T, NO>), grid, block, 0, s, a);
+}
+
+// Dealiased plan: fhat at n; the truncated series on the padded grid; the
+// padded operator's raw Q; its spectrum; back to the n modes; projection.
+template <typename T, int N, int NP>
+bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f, int f_fp32, const int32_t* idx,
+                           int ncells, const int32_t* ncells_dev, void* q, int scatter, hipStream_t s, bool timed,
+                           const bzk::ImexDev* imex) {
+  bz_plan* pm = const_cast<bz_plan*>(p);
+  char* ws = static_cast<char*>(b.ws);
+  const bz::WsLayout& lay = b.lay;
+  constexpr bool F32 = sizeof(T) == 4;
+  if (timed) {
+    pm->ev = &pm->evs[4 * (pm->timed_calls % bz_plan::kTimingSlots)];
+    (void)hipEventRecord(pm->ev[0], s);
+  }
+  PlainArgs<T> a{};
+  a.ncells = ncells;
+  a.ncells_dev = ncells_dev;
+  // 1. fhat at n (input rows idx[c])
+  a.f = f;
+  a.f_fp32 = f_fp32;
+  a.idx = idx;
+  a.fh = reinterpret_cast<cx<T>*>(ws + lay.fh_off);
+  a.fh_stride = lay.fh_cell / sizeof(cx<T>);
+  a.y = reinterpret_cast<cx<T>*>(ws + lay.y_off);
+  a.y_stride = lay.y_cell / sizeof(cx<T>);
+  launch_plain_forward<T, N>(a, ncells, s);
+  // 2. the truncated series sampled on the padded grid
+  a.acc = reinterpret_cast<T*>(ws + lay.fp_off);
+  a.acc_stride = lay.fp_cell / sizeof(T);
+  launch_resample<T, N, NP>(a, ncells, s);
+  if (timed) (void)hipEventRecord(pm->ev[1], s);
+  // 3. raw Q of the padded operator (compact cells)
+  const bz::Binding pb = bz::make_binding(p->pad, b.tables, ws + lay.pad_off, size_t(b.capacity) * lay.pad_cell);
+  bz_status st = bz::launch_collide(p->pad, pb, ws + lay.fp_off, F32 ? 1 : 0, nullptr, ncells, ncells_dev,
+                                    ws + lay.qp_off, 0, s, false);
+  if (st != BZ_OK) return st;
+  // 4. its spectrum on the padded grid
+  PlainArgs<T> c{};
+  c.ncells = ncells;
+  c.ncells_dev = ncells_dev;
+  c.f = ws + lay.qp_off;
+  c.f_fp32 = F32 ? 1 : 0;
+  c.idx = nullptr;
+  c.fh = reinterpret_cast<cx<T>*>(ws + lay.gp_off);
+  c.fh_stride = lay.gp_cell / sizeof(cx<T>);
+  c.y = reinterpret_cast<cx<T>*>(ws + lay.y_off);
+  c.y_stride = lay.y_cell / sizeof(cx<T>);
+  launch_plain_forward<T, NP>(c, ncells, s);
+  // 5. back to the n modes: Q at the n grid in the accumulator region
+  c.acc = reinterpret_cast<T*>(ws + lay.acc_off);
+  c.acc_stride = lay.acc_cell / sizeof(T);
+  launch_resample<T, NP, N>(c, ncells, s);
+  if (timed) (void)hipEventRecord(pm->ev[2], s);
+  // 6. projection / output (the padded Q already carries the kernel constant)
+  ProjArgs pa{};
+  pa.n = N;
+  pa.ncells = ncells;
+  pa.ncells_dev = ncells_dev;
+  pa.idx = idx;
+  pa.scatter = scatter;
+  pa.acc = ws + lay.acc_off;
+  pa.acc_fp32 = F32 ? 1 : 0;
+  pa.chunks = 1;
+  pa.acc_stride = lay.acc_cell / sizeof(T);
+  pa.C = 1.0;
+  pa.dv = p->dv;
+  for (int i = 0; i < 25; ++i) pa.ginv[i] = p->ginv[i];
+  pa.project = p->project;
+  pa.q = q;
+  pa.q_fp32 = p->fp32;
+  if (imex) {
+    pa.imex = 1;
+    pa.im = *imex;
+  }
+  hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  if (timed) {
+    (void)hipEventRecord(pm->ev[3], s);
+    pm->timed_calls += 1;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_collide_batch: launch failed: %s", hipGetErrorString(e));
+  return BZ_OK;
+}
+
 namespace bz {
 
 bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
@@ -1035,6 +1186,13 @@ int fused_default_chunks(int n) { return 1; }
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
                          int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex) {
+  if (p->pad) {
+    if (p->fp32)
+      return p->n == 16 ? launch_dealiased<float, 16, 24>(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed, imex)
+                        : launch_dealiased<float, 32, 48>(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed, imex);
+    return p->n == 16 ? launch_dealiased<double, 16, 24>(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed, imex)
+                      : launch_dealiased<double, 32, 48>(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed, imex);
+  }
   bz_plan* pm = const_cast<bz_plan*>(p);
   char* ws = static_cast<char*>(b.ws);
   const WsLayout& lay = b.lay;

@@ -331,7 +331,20 @@ void layout(bz_plan* p) {
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
   p->ws_fixed = 0;
-  p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell + p->ws.par_cell;
+  if (p->pad) {
+    // forward at n (fhat, scratch), f and raw Q on the padded grid, padded spectrum,
+    // Q resampled back (accumulator region), and the padded plan's own workspace
+    const size_t np3 = size_t(p->pad->n) * p->pad->n * p->pad->n;
+    p->ws.y_cell = align256(np3 * 2 * es);
+    p->ws.acc_cell = align256(n3 * es);
+    p->ws.fp_cell = align256(np3 * es);
+    p->ws.qp_cell = align256(np3 * es);
+    p->ws.gp_cell = align256(np3 * 2 * es);
+    p->ws.pad_cell = p->pad->ws_per_cell;
+    p->tables_bytes = p->pad->tables_bytes;  // the device tables are the padded operator's
+  }
+  p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell + p->ws.par_cell + p->ws.fp_cell +
+                   p->ws.qp_cell + p->ws.gp_cell + p->ws.pad_cell;
 }
 
 
@@ -348,10 +361,15 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
   b.lay.y_off = b.lay.fh_off + size_t(b.capacity) * b.lay.fh_cell;
   b.lay.acc_off = b.lay.y_off + size_t(b.capacity) * b.lay.y_cell;
   b.lay.par_off = b.lay.acc_off + size_t(b.capacity) * b.lay.acc_cell;
+  b.lay.fp_off = b.lay.par_off + size_t(b.capacity) * b.lay.par_cell;
+  b.lay.qp_off = b.lay.fp_off + size_t(b.capacity) * b.lay.fp_cell;
+  b.lay.gp_off = b.lay.qp_off + size_t(b.capacity) * b.lay.qp_cell;
+  b.lay.pad_off = b.lay.gp_off + size_t(b.capacity) * b.lay.gp_cell;
   return b;
 }
 
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
+  if (p->pad) return upload_tables(p->pad, tables_dev, s);
   const size_t n3 = size_t(p->n) * p->n * p->n;
   std::vector<unsigned char> host(p->tables_bytes, 0);
   const size_t entries = size_t(p->m1) * n3;
@@ -408,6 +426,9 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   if (d.max_cells < 1) return fail(BZ_ERR_ARG, "bz_plan_create: max_cells must be >= 1");
   if (d.chunks < 0 || d.chunks > d.m + 1) return fail(BZ_ERR_ARG, "bz_plan_create: chunks must be in 0..m+1");
   if (d.slices < 0 || d.slices > 2) return fail(BZ_ERR_ARG, "bz_plan_create: slices must be 0, 1 or 2");
+  if (d.dealias != 0 && d.dealias != 1) return fail(BZ_ERR_ARG, "bz_plan_create: dealias must be 0 or 1");
+  if (d.dealias && !(d.n == 16 || d.n == 32))
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: dealiased plans need n = 16 or 32 (padded 24 or 48)");
 
   bz_plan* p = new bz_plan();
   p->d = d;
@@ -477,8 +498,29 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
     delete p;
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel with %d slices for n=%d", slices, d.n);
   }
+  if (d.dealias) {
+    // the padded operator: same box, R, kernel and rule on 3n/2 points, raw Q in the plan precision
+    p->transform = BZ_XF_PLAIN;
+    p->chunks = 1;
+    bz_plan_desc pd = d;
+    pd.n = 3 * d.n / 2;
+    pd.R = R;
+    pd.dir_kind = BZ_DIRS_EXPLICIT;
+    pd.dirs = p->dirs.data();
+    pd.weights = p->w.data();
+    pd.project = 0;
+    pd.transform = BZ_XF_AUTO;
+    pd.chunks = 0;
+    pd.slices = 0;
+    pd.dealias = 0;
+    const bz_status st = bz_plan_create(&pd, &p->pad);
+    if (st != BZ_OK) {
+      delete p;
+      return st;
+    }
+  }
   build_tables(p);
-  if (!build_gram_inverse(p)) { delete p; return fail(BZ_ERR_NUMERIC, "bz_plan_create: Gram matrix not positive definite"); }
+  if (!build_gram_inverse(p)) { bz_plan_destroy(p->pad); delete p; return fail(BZ_ERR_NUMERIC, "bz_plan_create: Gram matrix not positive definite"); }
   layout(p);
   *out = p;
   return BZ_OK;
@@ -515,6 +557,7 @@ bz_status bz_plan_destroy(bz_plan* p) {
   clear_error();
   if (!p) return BZ_OK;
   for (auto& e : p->evs) (void)hipEventDestroy(e);
+  if (p->pad) bz_plan_destroy(p->pad);
   delete p;
   return BZ_OK;
 }

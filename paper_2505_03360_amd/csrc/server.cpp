@@ -97,7 +97,8 @@ struct PlanKey {
     return d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
            d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
            d.a2 == o.d.a2 && d.precision == o.d.precision && d.transform == o.d.transform &&
-           d.project == o.d.project && d.chunks == o.d.chunks && d.slices == o.d.slices && dirs == o.dirs &&
+           d.project == o.d.project && d.chunks == o.d.chunks && d.slices == o.d.slices &&
+           d.dealias == o.d.dealias && dirs == o.dirs &&
            weights == o.weights;
   }
 };

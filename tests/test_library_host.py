@@ -158,3 +158,21 @@ def test_pr222_validation():
             fn(p, d, *args)
         assert e.value.code == bz.BZ_ERR_STATE  # not bound
     bz.bz_plan_destroy(p)
+
+
+def test_dealias_plans():
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_create(bz.make_plan_desc(n=24, m=6, dealias=1))
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_create(bz.make_plan_desc(n=16, m=6, dealias=2))
+    assert e.value.code == bz.BZ_ERR_ARG
+    p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=6, dealias=1, precision=bz.BZ_FP64))
+    q = bz.bz_plan_create(bz.make_plan_desc(n=24, m=6, precision=bz.BZ_FP64, project=0))
+    tp, _, wp = bz.bz_plan_device_bytes(p)
+    tq, _, wq = bz.bz_plan_device_bytes(q)
+    assert tp == tq  # the device tables are the padded operator's
+    assert wp > wq  # its workspace holds the padded plan's plus the resampling buffers
+    assert bz.bz_plan_transform(p) == bz.BZ_XF_PLAIN
+    bz.bz_plan_destroy(p)
+    bz.bz_plan_destroy(q)
