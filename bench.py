@@ -275,6 +275,14 @@ def kinetic_run(col, f, steps: int):
     for _ in range(steps):
         col.imex_euler(f, tr, 0.01, eps=0.01, out=fo)
     ev[3].record()
+    zero = torch.zeros_like(f)
+    pr = col.pr222_step(f, lambda y: zero, 0.01, eps=0.01)
+    ev8 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev8[0].record()
+    for _ in range(steps):
+        col.pr222_step(f, lambda y: zero, 0.01, eps=0.01, out=pr)
+    ev8[1].record()
+    del pr
     qes = bz.esbgk_collide(f, L)
     ev[4].record()
     for _ in range(steps):
@@ -289,17 +297,41 @@ def kinetic_run(col, f, steps: int):
     mom_ms = ev[0].elapsed_time(ev[1]) / steps
     imex_ms = ev[2].elapsed_time(ev[3]) / steps
     es_ms = ev[4].elapsed_time(ev[5]) / steps
+    pr_ms = ev8[0].elapsed_time(ev8[1]) / steps
     esi_ms = ev[6].elapsed_time(ev[7]) / steps
     cells = f.shape[0]
     return {"moments_l1_ms": mom_ms,
             "moments_l1_compulsory_GB_s": cells * 8 * N ** 3 / (mom_ms * 1e-3) / 1e9,
             "imex_euler_ms": imex_ms, "imex_euler_cells_per_s": cells / (imex_ms * 1e-3),
+            "pr222_step_ms": pr_ms, "pr222_step_cells_per_s": cells / (pr_ms * 1e-3),
             "esbgk_collide_ms": es_ms,
             "esbgk_collide_compulsory_GB_s": cells * 16 * N ** 3 / (es_ms * 1e-3) / 1e9,
             "esbgk_imex_ms": esi_ms,
             "esbgk_imex_compulsory_GB_s": cells * 24 * N ** 3 / (esi_ms * 1e-3) / 1e9,
             "workload": f"{cells} cells N=32; M=32 FP32 collision + FP64 IMEX (eq. 1002), dt=0.01, eps=0.01; "
                         "ES-BGK beta=-1/2, mu0=1"}
+
+
+def dealias_run(f, q_circ, steps: int):
+    """The dealiased plan (truncated convolution without wrap-around, 3/2 rule)
+    on the same batch: time per batch and its distance from the circular one."""
+    import torch
+
+    import paper_2505_03360_amd as bz
+
+    col = bz.Collider(N, f.shape[0], L=L, m=M, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP32, dealias=1)
+    q = col(f)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        col(f, out=q)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    rel = float(torch.linalg.vector_norm(q - q_circ) / torch.linalg.vector_norm(q_circ))
+    col.close()
+    return {"ms_per_batch": ms, "cells_per_s": f.shape[0] / (ms * 1e-3), "rel_l2_vs_circular": rel,
+            "workload": f"{f.shape[0]} cells N=32 (padded 48) M=32 FP32 + FP64 projection"}
 
 
 def main():
@@ -411,6 +443,7 @@ def main():
         "algorithmic_tflops_whole_step": total_flops * value / 1e12,
     }
     rec["kinetic"] = kinetic_run(col, f, max(2, args.steps // 2))
+    rec["dealiased"] = dealias_run(f, out, max(2, args.steps // 4))
     if args.serve_seconds > 0:
         del out64, col64
         torch.cuda.empty_cache()
