@@ -235,3 +235,31 @@ def pr222_step(y: np.ndarray, transport, dt: float, eps: float, plan: spectral.P
     for i in range(2):
         out = out + dt * PR_W_EXP[i] * qs[i] + dt * PR_W_IMP[i] * gs[i] / eps
     return out
+
+
+def esbgk_stage_solve(r: np.ndarray, h: float, eps: float, L: float, beta: float, mu0: float) -> np.ndarray:
+    """Solution Y of Y = r + (h/eps) Q_ES(Y): the first-order ES-BGK step with
+    the transport removed (Q_ES conserves (1, v, |v|^2), so rho, u, T and nu of Y
+    are those of r, and the stress follows from the second-moment equation)."""
+    return esbgk_imex_euler(r, np.zeros_like(r), h, eps, L, beta, mu0)
+
+
+def esbgk_pr222_step(y: np.ndarray, transport, dt: float, eps: float, L: float, beta: float,
+                     mu0: float) -> np.ndarray:
+    """One PR(2,2,2) step of y' = -transport(y) + Q_ES(y)/eps (explicit part:
+    transport; implicit part: the ES-BGK relaxation), with the tableaux of
+    Sec. 4.3; each implicit stage solved by esbgk_stage_solve."""
+    n = y.shape[0]
+    Y, qs, gs = [], [], []
+    for i in range(2):
+        r = y.copy()
+        for j in range(i):
+            r = r + dt * PR_A_EXP[i, j] * qs[j] + dt * PR_A_IMP[i, j] * gs[j] / eps
+        Yi = esbgk_stage_solve(r, dt * PR_A_IMP[i, i], eps, L, beta, mu0)
+        Y.append(Yi)
+        qs.append(-transport(Yi))
+        gs.append(esbgk_collide(Yi, n, L, beta, mu0))
+    out = y.copy()
+    for i in range(2):
+        out = out + dt * PR_W_EXP[i] * qs[i] + dt * PR_W_IMP[i] * gs[i] / eps
+    return out

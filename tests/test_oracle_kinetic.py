@@ -293,3 +293,41 @@ def test_pr222_is_second_order_in_time():
         errs.append(np.linalg.norm(y - ref))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.5 <= r1 <= 5.0 and 3.5 <= r2 <= 5.0, errs
+
+
+def test_esbgk_stage_solve_solves_the_implicit_equation():
+    # Y = r + (h/eps) Q_ES(Y), checked by evaluating Q_ES at the returned Y
+    n, L, beta, mu0 = 48, 10.0, -0.5, 1.0
+    r = aniso(n, L, 1.0, [0.2, 0.1, -0.3], COV)
+    h, eps = 0.03, 0.05
+    Y = kinetic.esbgk_stage_solve(r, h, eps, L, beta, mu0)
+    res = Y - r - (h / eps) * kinetic.esbgk_collide(Y, n, L, beta, mu0)
+    assert np.abs(res).max() <= 1e-10 * np.abs(Y).max()
+
+
+def test_esbgk_pr222_order_and_conservation():
+    n, L, beta, mu0 = 24, 8.0, -0.5, 1.0
+    f = aniso(n, L, 1.0, [0.2, 0.1, -0.3], COV * 0.8) + aniso(n, L, 0.4, [-0.4, 0.2, 0.1], np.eye(3) * 0.9)
+    T = velocity_transport(n, L, [0.3, -0.2, 0.1])
+    eps, t_end = 2.0, 0.2
+    # conservation: int phi y^{n+1} = int phi y - dt/2 int phi (T(Y1) + T(Y2)); checked through a step with T = 0
+    zero = lambda y: np.zeros_like(y)
+    out = kinetic.esbgk_pr222_step(f, zero, 0.05, eps, L, beta, mu0)
+    U = kinetic.conserved(f, n, L)
+    assert np.abs(kinetic.conserved(out, n, L) - U).max() <= 1e-10 * np.abs(U).max()
+    # second order in time against RK4 on the same equation
+    def rhs(y):
+        return -T(y) + kinetic.esbgk_collide(y, n, L, beta, mu0) / eps
+    ref = f.copy()
+    h = t_end / 64
+    for _ in range(64):
+        k1 = rhs(ref); k2 = rhs(ref + 0.5 * h * k1); k3 = rhs(ref + 0.5 * h * k2); k4 = rhs(ref + h * k3)
+        ref = ref + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    errs = []
+    for steps in (4, 8, 16):
+        y = f.copy()
+        for _ in range(steps):
+            y = kinetic.esbgk_pr222_step(y, T, t_end / steps, eps, L, beta, mu0)
+        errs.append(np.linalg.norm(y - ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 <= r1 <= 5.0 and 3.5 <= r2 <= 5.0, errs
