@@ -316,6 +316,31 @@ bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* desc, const bz_imex_desc* ime
                               const double* tr, const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
                               double* f_out, int32_t flags, void* stream);
 
+/*
+ * The ES-BGK layer with the second-order PR(2,2,2) IMEX scheme (Sec. 4.3):
+ * explicit part -v.grad_x y, implicit part Q_ES(y)/eps.  Each implicit stage
+ * Y = R + (h/eps) Q_ES(Y) is solved explicitly like the first-order step
+ * (no transport, dt -> h = gamma dt).  Split where the caller evaluates the
+ * transport of the stage values:
+ *   stage 1:  Y1 = S_ES(y, gamma dt)
+ *   [caller:  T1 = v . grad_x Y1]
+ *   stage 2:  R2 = y - dt T1 + (1 - 2 gamma) dt Q_ES(Y1)/eps,  Y2 = S_ES(R2, gamma dt),
+ *             A = y - (dt/2) T1 + (dt/(2 eps)) Q_ES(Y1)
+ *   [caller:  T2 = v . grad_x Y2]
+ *   finish:   y_out = A - (dt/2) T2 + (dt/(2 eps)) Q_ES(Y2)
+ * Arrays, rows and aliasing as for bz_pr222_*; in the finish y_out may also
+ * be `a` itself.
+ */
+bz_status bz_esbgk_pr222_stage1(const bz_esbgk_desc* desc, const bz_imex_desc* imex, const double* y,
+                                const int32_t* idx, int32_t ncells, const int32_t* ncells_dev, double* y1,
+                                void* stream);
+bz_status bz_esbgk_pr222_stage2(const bz_esbgk_desc* desc, const bz_imex_desc* imex, const double* y,
+                                const double* y1, const double* t1, const int32_t* idx, int32_t ncells,
+                                const int32_t* ncells_dev, double* y2, double* a, void* stream);
+bz_status bz_esbgk_pr222_finish(const bz_esbgk_desc* desc, const bz_imex_desc* imex, const double* a,
+                                const double* y2, const double* t2, const int32_t* idx, int32_t ncells,
+                                const int32_t* ncells_dev, double* y_out, void* stream);
+
 
 typedef struct {
   int32_t nx, ny;           /* spatial grid, arrays are row-major [iy][ix] */

@@ -140,6 +140,12 @@ SIGNATURES = [
     ("bz_pr222_stage1", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _I32, _VP, _VP, _VP]),
     ("bz_pr222_stage2", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP]),
     ("bz_pr222_finish", _I32, [_VP, ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP]),
+    ("bz_esbgk_pr222_stage1", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _I32, _VP,
+                                     _VP, _VP]),
+    ("bz_esbgk_pr222_stage2", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP,
+                                     _I32, _VP, _VP, _VP, _VP]),
+    ("bz_esbgk_pr222_finish", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _VP,
+                                     _I32, _VP, _VP, _VP]),
     ("bz_esbgk_collide", _I32, [ctypes.POINTER(BzEsbgkDesc), _VP, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_esbgk_imex_euler", _I32, [ctypes.POINTER(BzEsbgkDesc), ctypes.POINTER(BzImexDesc), _VP, _VP, _VP, _I32,
                                    _VP, _VP, _I32, _VP]),
@@ -297,6 +303,23 @@ def bz_pr222_stage2(plan: int, desc: BzImexDesc, y: int, y1: int, t1: int, idx: 
 def bz_pr222_finish(plan: int, desc: BzImexDesc, a: int, y2: int, t2: int, idx: int, ncells: int,
                     ncells_dev: int, y_out: int, stream: int = 0) -> None:
     _check(lib().bz_pr222_finish(plan, ctypes.byref(desc), a, y2, t2, idx, ncells, ncells_dev, y_out, stream))
+
+
+def bz_esbgk_pr222_stage1(desc: BzEsbgkDesc, imex: BzImexDesc, y: int, idx: int, ncells: int, ncells_dev: int,
+                          y1: int, stream: int = 0) -> None:
+    _check(lib().bz_esbgk_pr222_stage1(ctypes.byref(desc), ctypes.byref(imex), y, idx, ncells, ncells_dev, y1, stream))
+
+
+def bz_esbgk_pr222_stage2(desc: BzEsbgkDesc, imex: BzImexDesc, y: int, y1: int, t1: int, idx: int, ncells: int,
+                          ncells_dev: int, y2: int, a: int, stream: int = 0) -> None:
+    _check(lib().bz_esbgk_pr222_stage2(ctypes.byref(desc), ctypes.byref(imex), y, y1, t1, idx, ncells, ncells_dev,
+                                       y2, a, stream))
+
+
+def bz_esbgk_pr222_finish(desc: BzEsbgkDesc, imex: BzImexDesc, a: int, y2: int, t2: int, idx: int, ncells: int,
+                          ncells_dev: int, y_out: int, stream: int = 0) -> None:
+    _check(lib().bz_esbgk_pr222_finish(ctypes.byref(desc), ctypes.byref(imex), a, y2, t2, idx, ncells, ncells_dev,
+                                       y_out, stream))
 
 
 def bz_esbgk_collide(desc: BzEsbgkDesc, f: int, idx: int, ncells: int, ncells_dev: int, q: int,
@@ -520,6 +543,23 @@ def esbgk_imex_euler(f, tr, L: float, dt: float, eps: float = 0.0, eps_cells=Non
     bz_esbgk_imex_euler(BzEsbgkDesc(n, L, beta, mu0), BzImexDesc(dt, eps, _ptr(eps_cells)), _ptr(f), _ptr(tr),
                         _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out), BZ_SCATTER if scatter else 0,
                         _stream(stream))
+    return out
+
+
+def esbgk_pr222_step(y, transport, L: float, dt: float, eps: float = 0.0, eps_cells=None, beta: float = -0.5,
+                     mu0: float = 1.0, idx=None, out=None, stream=None):
+    """One PR(2,2,2) step of the ES-BGK layer through bz_esbgk_pr222_*;
+    `transport` maps a stage value to v . grad_x of it between the calls."""
+    torch = _torch()
+    n, ncells = _f64_cells(y, idx, None)
+    desc, im, st = BzEsbgkDesc(n, L, beta, mu0), BzImexDesc(dt, eps, _ptr(eps_cells)), _stream(stream)
+    y1, y2, a = torch.empty_like(y), torch.empty_like(y), torch.empty_like(y)
+    out = torch.empty_like(y) if out is None else out
+    bz_esbgk_pr222_stage1(desc, im, _ptr(y), _ptr(idx), ncells, 0, _ptr(y1), st)
+    t1 = transport(y1).contiguous()
+    bz_esbgk_pr222_stage2(desc, im, _ptr(y), _ptr(y1), _ptr(t1), _ptr(idx), ncells, 0, _ptr(y2), _ptr(a), st)
+    t2 = transport(y2).contiguous()
+    bz_esbgk_pr222_finish(desc, im, _ptr(a), _ptr(y2), _ptr(t2), _ptr(idx), ncells, 0, _ptr(out), st)
     return out
 
 

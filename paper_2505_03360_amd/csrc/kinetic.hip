@@ -181,13 +181,24 @@ struct EsArgs {
   const int32_t* ncells_dev;
   const int32_t* idx;
   int scatter;
-  const double* f;
-  const double* tr;         // IMEX: transport term (rows as f)
-  const double* eps_cells;  // IMEX: Knudsen number per row, or null
-  double eps, dt;           // IMEX
+  const double* f;          // the distribution (or stage value) whose moments define G
+  const double* tr;         // IMEX: transport term (rows as f; null = none); PR stages: T_i
+  const double* eps_cells;  // Knudsen number per row, or null
+  double eps, dt;
   double beta, mu0, dv;
   double* out;
+  const double* y;  // PR stage 2: y^n
+  double* aux;      // PR: A (written by stage 2, read by the finish)
 };
+
+enum EsMode {
+  ES_COLLIDE = 0,  // out = nu (G[f] - f)
+  ES_IMEX = 1,     // out = c g + (1 - c) G, g = f - dt tr (stage solve when tr is null)
+  ES_PR_STAGE2 = 2,  // g1 = Q_ES(Y1): out = y - dt T1 + dt a21 g1/eps, aux = y - dt/2 T1 + dt/(2 eps) g1
+  ES_PR_FINISH = 3,  // g2 = Q_ES(Y2): out = aux - dt/2 T2 + dt/(2 eps) g2
+};
+
+constexpr double kPrA21 = 0.41421356237309505;  // 1 - 2 gamma = sqrt(2) - 1
 
 // ES-BGK (Sec. 2.2), one cell per workgroup.
 //   collision:  Q_ES = nu (G[f] - f), G from f's density, velocity and stress;
@@ -197,8 +208,9 @@ struct EsArgs {
 //     c = eps / (eps + nu dt).
 // G = rho (2 pi)^(-3/2) det(Tau)^(-1/2) exp(-(v-u) Tau^-1 (v-u) / 2),
 // Tau = (1 - beta) T I + beta Theta; nu = rho sqrt(T) / (mu0 (1 - beta)).
-template <int N, bool IMEX>
+template <int N, int MODE>
 __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
+  constexpr bool IMEX = MODE == ES_IMEX;
   constexpr int N3 = N * N * N;
   __shared__ double red[10 * kWaves];
   const int c = blockIdx.x;
@@ -206,9 +218,9 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   const int t = threadIdx.x;
   const long row = a.idx ? long(a.idx[c]) : long(c);
   const double* f = a.f + size_t(row) * N3;
-  const double* tr = IMEX ? a.tr + size_t(row) * N3 : nullptr;
+  const double* tr = a.tr ? a.tr + size_t(row) * N3 : nullptr;
   auto h = [&](int j) -> double {
-    if constexpr (IMEX) return f[j] - a.dt * tr[j];
+    if constexpr (IMEX) return tr ? f[j] - a.dt * tr[j] : f[j];
     else return f[j];
   };
   // sums of h, v h, v_a v_b h (11, 22, 33, 12, 13, 23)
@@ -239,8 +251,8 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   const double T = (th[0] + th[1] + th[2]) / 3.0;
   const double nu = rho * sqrt(T) / (a.mu0 * (1.0 - a.beta));
   [[maybe_unused]] double cmix = 0.0;
+  const double eps = a.eps_cells ? a.eps_cells[row] : a.eps;
   if constexpr (IMEX) {
-    const double eps = a.eps_cells ? a.eps_cells[row] : a.eps;
     const double am = eps / (eps + (1.0 - a.beta) * nu * a.dt);
     // Sigma / rho - u u with Sigma = am S(g) + (1 - am) rho (T I + u u)
 #pragma unroll
@@ -258,15 +270,27 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   const double id = 1.0 / det;
   const double i11 = c11 * id, i22 = c22 * id, i33 = c33 * id, i12 = c12 * id, i13 = c13 * id, i23 = c23 * id;
   const double cg = rho / sqrt(8.0 * M_PI * M_PI * M_PI * det);
-  double* out = a.out + size_t(a.scatter ? row : long(c)) * N3;
+  const size_t orow = size_t(a.scatter ? row : long(c)) * N3;
+  double* out = a.out + orow;
   for (int j = t; j < N3; j += kThreads) {
     const double d1 = node<N>(j / (N * N), a.dv) - u[0], d2 = node<N>((j / N) % N, a.dv) - u[1],
                  d3 = node<N>(j % N, a.dv) - u[2];
     const double quad = i11 * d1 * d1 + i22 * d2 * d2 + i33 * d3 * d3 +
                         2.0 * (i12 * d1 * d2 + i13 * d1 * d3 + i23 * d2 * d3);
     const double G = cg * exp(-0.5 * quad);
-    if constexpr (IMEX) out[j] = cmix * h(j) + (1.0 - cmix) * G;
-    else out[j] = nu * (G - f[j]);
+    if constexpr (MODE == ES_IMEX) {
+      out[j] = cmix * h(j) + (1.0 - cmix) * G;
+    } else if constexpr (MODE == ES_COLLIDE) {
+      out[j] = nu * (G - f[j]);
+    } else if constexpr (MODE == ES_PR_STAGE2) {
+      const double g1 = nu * (G - f[j]);
+      const double y = a.y[orow + j], t1 = tr[j];
+      out[j] = y - a.dt * t1 + (a.dt * kPrA21 / eps) * g1;
+      a.aux[orow + j] = y - 0.5 * a.dt * t1 + (0.5 * a.dt / eps) * g1;
+    } else {
+      const double g2 = nu * (G - f[j]);
+      out[j] = a.aux[orow + j] - 0.5 * a.dt * tr[j] + (0.5 * a.dt / eps) * g2;
+    }
   }
 }
 
@@ -472,15 +496,15 @@ bz_status esbgk_check(const char* who, const bz_esbgk_desc* d, int32_t ncells, i
   return BZ_OK;
 }
 
-template <bool IMEX>
+template <int MODE>
 bz_status esbgk_launch(const bz_esbgk_desc* d, const EsArgs& a, int ncells, void* stream, const char* who) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(ncells)), block(kThreads);
   switch (d->n) {
-    case 16: hipLaunchKernelGGL((k_esbgk<16, IMEX>), grid, block, 0, s, a); break;
-    case 24: hipLaunchKernelGGL((k_esbgk<24, IMEX>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_esbgk<32, IMEX>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_esbgk<48, IMEX>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_esbgk<16, MODE>), grid, block, 0, s, a); break;
+    case 24: hipLaunchKernelGGL((k_esbgk<24, MODE>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_esbgk<32, MODE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_esbgk<48, MODE>), grid, block, 0, s, a); break;
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
@@ -507,7 +531,7 @@ extern "C" bz_status bz_esbgk_collide(const bz_esbgk_desc* d, const double* f, c
   a.mu0 = d->mu0;
   a.dv = 2.0 * d->L / d->n;
   a.out = q;
-  return esbgk_launch<false>(d, a, ncells, stream, "bz_esbgk_collide");
+  return esbgk_launch<ES_COLLIDE>(d, a, ncells, stream, "bz_esbgk_collide");
 }
 
 extern "C" bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* d, const bz_imex_desc* im, const double* f,
@@ -537,7 +561,7 @@ extern "C" bz_status bz_esbgk_imex_euler(const bz_esbgk_desc* d, const bz_imex_d
   a.mu0 = d->mu0;
   a.dv = 2.0 * d->L / d->n;
   a.out = f_out;
-  return esbgk_launch<true>(d, a, ncells, stream, "bz_esbgk_imex_euler");
+  return esbgk_launch<ES_IMEX>(d, a, ncells, stream, "bz_esbgk_imex_euler");
 }
 
 // ---------------------------------------------------------------- PR(2,2,2) entry points
@@ -635,4 +659,94 @@ extern "C" bz_status bz_pr222_finish(const bz_plan* p, const bz_imex_desc* d, co
   a.t1 = t2;
   a.out = y_out;
   return launch_pr(3, p->n, ncells, a, s);
+}
+
+// ---------------------------------------------------------------- ES-BGK PR(2,2,2)
+namespace {
+
+bz_status es_pr_check(const char* who, const bz_esbgk_desc* d, const bz_imex_desc* im, int32_t ncells) {
+  bz_status st = esbgk_check(who, d, ncells, 0, nullptr);
+  if (st != BZ_OK) return st;
+  if (!im) return bz::fail(BZ_ERR_ARG, "%s: null IMEX descriptor", who);
+  if (!(im->dt > 0.0) || !std::isfinite(im->dt)) return bz::fail(BZ_ERR_ARG, "%s: dt must be > 0", who);
+  if (!im->eps_cells && !(im->eps > 0.0)) return bz::fail(BZ_ERR_ARG, "%s: eps must be > 0", who);
+  return BZ_OK;
+}
+
+EsArgs es_pr_args(const bz_esbgk_desc* d, const bz_imex_desc* im, const int32_t* idx, int ncells,
+                  const int32_t* ncells_dev) {
+  EsArgs a{};
+  a.ncells = ncells;
+  a.ncells_dev = ncells_dev;
+  a.idx = idx;
+  a.scatter = 1;  // every array is indexed by the cell's row
+  a.eps_cells = im->eps_cells;
+  a.eps = im->eps;
+  a.beta = d->beta;
+  a.mu0 = d->mu0;
+  a.dv = 2.0 * d->L / d->n;
+  return a;
+}
+
+}  // namespace
+
+extern "C" bz_status bz_esbgk_pr222_stage1(const bz_esbgk_desc* d, const bz_imex_desc* im, const double* y,
+                                           const int32_t* idx, int32_t ncells, const int32_t* ncells_dev, double* y1,
+                                           void* stream) {
+  bz::clear_error();
+  bz_status st = es_pr_check("bz_esbgk_pr222_stage1", d, im, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!y || !y1) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_stage1: null y or y1");
+  if (y1 == y) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_stage1: y1 must not alias y");
+  EsArgs a = es_pr_args(d, im, idx, ncells, ncells_dev);
+  a.f = y;
+  a.tr = nullptr;
+  a.dt = kPrGamma * im->dt;  // the implicit stage: Y1 = y + gamma dt Q_ES(Y1)/eps
+  a.out = y1;
+  return esbgk_launch<ES_IMEX>(d, a, ncells, stream, "bz_esbgk_pr222_stage1");
+}
+
+extern "C" bz_status bz_esbgk_pr222_stage2(const bz_esbgk_desc* d, const bz_imex_desc* im, const double* y,
+                                           const double* y1, const double* t1, const int32_t* idx, int32_t ncells,
+                                           const int32_t* ncells_dev, double* y2, double* a_out, void* stream) {
+  bz::clear_error();
+  bz_status st = es_pr_check("bz_esbgk_pr222_stage2", d, im, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!y || !y1 || !t1 || !y2 || !a_out) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_stage2: null array");
+  const void* in[3] = {y, y1, t1};
+  for (const void* q : in)
+    if (q == y2 || q == a_out) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_stage2: outputs must not alias inputs");
+  if (y2 == a_out) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_stage2: y2 and a must differ");
+  EsArgs a = es_pr_args(d, im, idx, ncells, ncells_dev);
+  a.f = y1;
+  a.tr = t1;
+  a.y = y;
+  a.dt = im->dt;
+  a.out = y2;  // R2
+  a.aux = a_out;
+  st = esbgk_launch<ES_PR_STAGE2>(d, a, ncells, stream, "bz_esbgk_pr222_stage2");
+  if (st != BZ_OK) return st;
+  EsArgs b = es_pr_args(d, im, idx, ncells, ncells_dev);
+  b.f = y2;  // in place: Y2 = S(R2, gamma dt)
+  b.tr = nullptr;
+  b.dt = kPrGamma * im->dt;
+  b.out = y2;
+  return esbgk_launch<ES_IMEX>(d, b, ncells, stream, "bz_esbgk_pr222_stage2");
+}
+
+extern "C" bz_status bz_esbgk_pr222_finish(const bz_esbgk_desc* d, const bz_imex_desc* im, const double* a_in,
+                                           const double* y2, const double* t2, const int32_t* idx, int32_t ncells,
+                                           const int32_t* ncells_dev, double* y_out, void* stream) {
+  bz::clear_error();
+  bz_status st = es_pr_check("bz_esbgk_pr222_finish", d, im, ncells);
+  if (st != BZ_OK || ncells == 0) return st;
+  if (!a_in || !y2 || !t2 || !y_out) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_finish: null array");
+  if (y_out == y2 || y_out == t2) return bz::fail(BZ_ERR_ARG, "bz_esbgk_pr222_finish: y_out must not alias y2 or t2");
+  EsArgs a = es_pr_args(d, im, idx, ncells, ncells_dev);
+  a.f = y2;
+  a.tr = t2;
+  a.dt = im->dt;
+  a.aux = const_cast<double*>(a_in);
+  a.out = y_out;  // may equal a_in (same element, same thread)
+  return esbgk_launch<ES_PR_FINISH>(d, a, ncells, stream, "bz_esbgk_pr222_finish");
 }

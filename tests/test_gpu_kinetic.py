@@ -214,3 +214,24 @@ def test_pr222_against_oracle(n, rule, m, prec):
         print(f"  row {r}: err {err:.3e} bound {bound:.3e}", flush=True)
         assert err <= bound
     col.close()
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_esbgk_pr222_against_oracle(n):
+    import paper_2505_03360_amd as bz
+    print("case esbgk pr222", n, flush=True)
+    L, dt, eps, beta, mu0 = 8.0, 0.01, 0.05, -0.5, 1.0
+    f = gen.shock_batch(4, n, L, seed=80 + n)
+    rows = [1, 3]
+    v = spectral.velocity_nodes(n, L)
+    V1, V2, V3 = np.meshgrid(v, v, v, indexing="ij")
+    wv = 0.4 * V1 - 0.3 * V2 + 0.2 * V3
+    ref = [kinetic.esbgk_pr222_step(f[r], lambda z: wv * z, dt, eps, L, beta, mu0) for r in rows]
+    ft = torch.from_numpy(f).cuda()
+    wt = torch.from_numpy(wv).cuda()
+    idx = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    out = bz.esbgk_pr222_step(ft, lambda z: z * wt, L, dt, eps=eps, beta=beta, mu0=mu0, idx=idx).cpu().numpy()
+    for c, r in enumerate(rows):
+        err = np.linalg.norm(out[r] - ref[c]) / np.linalg.norm(ref[c])
+        print(f"  row {r}: err {err:.3e}", flush=True)
+        assert err <= 1e-12

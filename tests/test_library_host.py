@@ -176,3 +176,15 @@ def test_dealias_plans():
     assert bz.bz_plan_transform(p) == bz.BZ_XF_PLAIN
     bz.bz_plan_destroy(p)
     bz.bz_plan_destroy(q)
+
+
+def test_esbgk_pr222_validation():
+    d, im = bz.BzEsbgkDesc(32, 8.0, -0.5, 1.0), bz.BzImexDesc(0.01, 0.1, None)
+    for fn, args in ((bz.bz_esbgk_pr222_stage1, (0, 0, 1, 0, 0)), (bz.bz_esbgk_pr222_stage2, (0, 0, 0, 0, 1, 0, 0, 0)),
+                     (bz.bz_esbgk_pr222_finish, (0, 0, 0, 0, 1, 0, 0))):
+        with pytest.raises(bz.BzError) as e:
+            fn(d, im, *args)
+        assert e.value.code == bz.BZ_ERR_ARG  # null arrays
+        with pytest.raises(bz.BzError) as e:
+            fn(d, bz.BzImexDesc(-1.0, 0.1, None), *args)
+        assert e.value.code == bz.BZ_ERR_ARG  # dt <= 0
