@@ -37,7 +37,10 @@ def test_dealiased_against_oracle(n, rule, m, prec):
         err = spectral.rel_err(q[c], ref[c], loss[c])
         print(f"  cell {c}: err {err:.3e}", flush=True)
         assert err <= tol
-    # the dealiased operator differs from the circular one by the wrapped terms
-    circ = spectral.project(spectral.collide(f[rows[0]], plan), n, L)
-    assert np.linalg.norm(ref[0] - circ) > 1e-4 * np.linalg.norm(ref[0])
+    if prec == "fp64":
+        # the result is the dealiased operator, not the circular one (their
+        # difference on these cells, ~1e-4 of ||Q||, is below FP32 rounding of
+        # the gain and loss terms, so this is checked in FP64)
+        circ = spectral.project(spectral.collide(f[rows[0]], plan), n, L)
+        assert np.linalg.norm(ref[0] - circ) > 1e3 * np.linalg.norm(q[0] - ref[0])
     col.close()
