@@ -191,6 +191,13 @@ bz_status bz_collide_batch(const bz_plan* plan, const void* f, int32_t f_dtype,
                            const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
                            void* q, int32_t flags, void* stream);
 
+/* Numeric status of the plan's evaluations: waits for `stream`, then returns
+   BZ_ERR_NUMERIC (and clears the flag) if any bz_collide_batch /
+   bz_imex_euler / bz_pr222_* output written through this plan's binding since
+   the last sync (or bind) held a non-finite value (e.g. from a NaN in f),
+   else BZ_OK.  Evaluations never stop on such values: they are reported. */
+bz_status bz_plan_sync(bz_plan* plan, void* stream);
+
 /* Per-stage GPU timing of bz_collide_batch, for measurement.  When enabled,
    each call records HIP events on its stream around the forward transform,
    the direction/loss kernel(s) and the projection (up to 512 calls are
@@ -399,7 +406,8 @@ bz_status bz_realizability_mask(const bz_mask_desc* desc, const double* rho, con
  * bz_serve_poll reports DONE or FAILED.  A request's result does not depend
  * on the other requests in flight.  A request whose descriptor is invalid
  * or whose workspace can never fit in the arena ends FAILED (err set) without
- * affecting the others.
+ * affecting the others; one whose output holds a non-finite value ends FAILED
+ * with BZ_ERR_NUMERIC (its output is written).
  */
 typedef struct bz_server bz_server;
 

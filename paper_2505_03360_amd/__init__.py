@@ -133,6 +133,7 @@ SIGNATURES = [
     ("bz_plan_get_rule", _I32, [_VP, _c_double_p, _c_double_p]),
     ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
     ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_plan_sync", _I32, [_VP, _VP]),
     ("bz_plan_set_timing", _I32, [_VP, _I32]),
     ("bz_cell_moments", _I32, [_I32, ctypes.c_double, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(BzMomentsOut),
                                _I32, _VP]),
@@ -331,6 +332,10 @@ def bz_esbgk_imex_euler(desc: BzEsbgkDesc, imex: BzImexDesc, f: int, tr: int, id
                         ncells_dev: int, f_out: int, flags: int = 0, stream: int = 0) -> None:
     _check(lib().bz_esbgk_imex_euler(ctypes.byref(desc), ctypes.byref(imex), f, tr, idx, ncells, ncells_dev,
                                      f_out, flags, stream))
+
+
+def bz_plan_sync(plan: int, stream: int = 0) -> None:
+    _check(lib().bz_plan_sync(plan, stream))
 
 
 def bz_plan_set_timing(plan: int, enable: bool) -> None:

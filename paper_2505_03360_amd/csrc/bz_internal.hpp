@@ -19,8 +19,13 @@ void clear_error();
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Every workspace starts with a status region: int32 word 0 is set by the
+// output epilogues when they write a non-finite value.
+constexpr size_t kStatusBytes = 256;
+
 // Workspace regions of a bound plan, each [capacity][...].
 struct WsLayout {
+  size_t status_off = 0;                  // byte offset of the status word
   size_t fh_off, y_off, acc_off, par_off;  // byte offsets into ws_dev
   size_t fh_cell, y_cell, acc_cell, par_cell;  // bytes per cell of each region
   // dealiased plans: padded f, padded raw Q, padded spectrum, the padded plan's workspace
@@ -81,6 +86,8 @@ namespace bz {
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
                          int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex = nullptr);
+// clears a status word with a vector store (collide.hip)
+void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s);
 // per-cell IMEX parameters (kinetic.hip)
 bool kinetic_n_supported(int n);
 bz_status launch_imex_params(int n, double dv, const int32_t* idx, int ncells, const int32_t* ncells_dev,

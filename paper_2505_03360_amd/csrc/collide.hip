@@ -44,6 +44,16 @@ __device__ __forceinline__ int live_count(int ncells, const int32_t* ncells_dev)
   return c;
 }
 
+// Records a non-finite output in the status word.  The address depends on the
+// lane through a run-time zero, so the store is a vector store.
+__device__ __forceinline__ void flag_nonfinite(int32_t* status, int zero, bool bad) {
+  if (bad && status) status[threadIdx.x * zero] = 1;
+}
+
+__global__ void k_clear_status(int32_t* status, int zero) {
+  if (threadIdx.x == 0) status[threadIdx.x * zero] = 0;
+}
+
 template <typename T>
 struct PlainArgs {
   const void* f;
@@ -424,6 +434,8 @@ struct FusedArgs {
   double C, dv;
   double ginv[25];
   double* q;
+  int32_t* status;   // set to 1 when a non-finite value is written
+  int zero;           // 0 at run time: keeps the status store a per-lane (vector) store
   int imex;           // write the IMEX update of eq. 1002 instead of Q (projection epilogue only;
                       // selects the IMEX instantiation of the kernel)
   bzk::ImexDev im;
@@ -801,6 +813,7 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
     const long orow = a.scatter ? row : long(cell);
     double* q = a.q + size_t(orow) * N * N * N;
     [[maybe_unused]] const double eps_c = IMEX ? (a.im.eps_cells ? a.im.eps_cells[row] : a.im.eps) : 0.0;
+    bool bad = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const double v3 = (s * W + tl - N / 2) * a.dv;
@@ -810,15 +823,17 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
         const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
         const size_t e = size_t(j1) * N * N + size_t(j2) * N + s * W + tl;
         const double qv = a.C * double(acc[s][j1]) - corr;
+        double ov = qv;
         if constexpr (IMEX) {
           const size_t fe = size_t(row) * N * N * N + e;
-          q[e] = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c,
-                                 a.im.dt, v1, v2, v3);
-        } else {
-          q[e] = qv;
+          ov = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c,
+                               a.im.dt, v1, v2, v3);
         }
+        q[e] = ov;
+        bad |= !isfinite(ov);
       }
     }
+    flag_nonfinite(a.status, a.zero, bad);
     return;
   }
   float* out = a.acc + cell * a.acc_stride + size_t(chunk) * N * N * N;
@@ -846,6 +861,8 @@ struct ProjArgs {
   int q_fp32;   // output type when project == 0
   int imex;     // write the IMEX update of eq. 1002 (FP64) instead of Q
   bzk::ImexDev im;
+  int32_t* status;  // set to 1 when a non-finite value is written
+  int zero;         // 0 at run time (per-lane store address)
 };
 
 __device__ __forceinline__ double load_acc(const ProjArgs& a, size_t i) {
@@ -877,8 +894,14 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     return bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
                            v1, v2, v3);
   };
+  bool bad = false;
   if (!a.project && a.imex) {
-    for (size_t j = t; j < n3; j += blockDim.x) static_cast<double*>(a.q)[row * n3 + j] = imex_out(j, qraw(j));
+    for (size_t j = t; j < n3; j += blockDim.x) {
+      const double v = imex_out(j, qraw(j));
+      static_cast<double*>(a.q)[row * n3 + j] = v;
+      bad |= !isfinite(v);
+    }
+    flag_nonfinite(a.status, a.zero, bad);
     return;
   }
   if (!a.project) {
@@ -886,7 +909,9 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
       const double v = qraw(j);
       if (a.q_fp32) static_cast<float*>(a.q)[row * n3 + j] = float(v);
       else static_cast<double*>(a.q)[row * n3 + j] = v;
+      bad |= !isfinite(v);
     }
+    flag_nonfinite(a.status, a.zero, bad);
     return;
   }
   double m[5] = {0, 0, 0, 0, 0};
@@ -923,8 +948,11 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
     const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
     const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
-    q[j] = a.imex ? imex_out(j, qraw(j) - corr) : qraw(j) - corr;
+    const double v = a.imex ? imex_out(j, qraw(j) - corr) : qraw(j) - corr;
+    q[j] = v;
+    bad |= !isfinite(v);
   }
+  flag_nonfinite(a.status, a.zero, bad);
 }
 
 // Projection of a plane-major accumulator acc[cell][j3][j1][j2] (one chunk,
@@ -974,6 +1002,7 @@ __global__ __launch_bounds__(256) void k_project_pm(ProjArgs a) {
     }
   }
   const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
+  bool bad = false;
   for (size_t J0 = 0; J0 < n2; J0 += 32) {
     __syncthreads();  // the previous tile has been written out
     for (int i = t; i < n * 32; i += blockDim.x) {
@@ -991,15 +1020,15 @@ __global__ __launch_bounds__(256) void k_project_pm(ProjArgs a) {
       if (a.project) qv -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
       if (a.imex) {
         const size_t fe = frow * n3 + j;
-        static_cast<double*>(a.q)[row * n3 + j] = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe],
-                                                                  a.im.tr[fe], eps_c, a.im.dt, v1, v2, v3);
-      } else if (a.project || !a.q_fp32) {
-        static_cast<double*>(a.q)[row * n3 + j] = qv;
-      } else {
-        static_cast<float*>(a.q)[row * n3 + j] = float(qv);
+        qv = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
+                             v1, v2, v3);
       }
+      if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * n3 + j] = qv;
+      else static_cast<float*>(a.q)[row * n3 + j] = float(qv);
+      bad |= !isfinite(qv);
     }
   }
+  flag_nonfinite(a.status, a.zero, bad);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1123,7 +1152,8 @@ bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f
   launch_resample<T, N, NP>(a, ncells, s);
   if (timed) (void)hipEventRecord(pm->ev[1], s);
   // 3. raw Q of the padded operator (compact cells)
-  const bz::Binding pb = bz::make_binding(p->pad, b.tables, ws + lay.pad_off, size_t(b.capacity) * lay.pad_cell);
+  const bz::Binding pb = bz::make_binding(p->pad, b.tables, ws + lay.pad_off,
+                                          p->pad->ws_fixed + size_t(b.capacity) * lay.pad_cell);
   bz_status st = bz::launch_collide(p->pad, pb, ws + lay.fp_off, F32 ? 1 : 0, nullptr, ncells, ncells_dev,
                                     ws + lay.qp_off, 0, s, false);
   if (st != BZ_OK) return st;
@@ -1161,6 +1191,7 @@ bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f
   pa.project = p->project;
   pa.q = q;
   pa.q_fp32 = p->fp32;
+  pa.status = reinterpret_cast<int32_t*>(ws + lay.status_off);
   if (imex) {
     pa.imex = 1;
     pa.im = *imex;
@@ -1176,6 +1207,11 @@ bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f
 }
 
 namespace bz {
+
+void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<int32_t*>(static_cast<char*>(ws) + lay.status_off), 0);
+}
 
 bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
 
@@ -1217,6 +1253,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   pa.project = p->project;
   pa.q = q;
   pa.q_fp32 = p->fp32;
+  pa.status = reinterpret_cast<int32_t*>(ws + lay.status_off);
   if (imex) {
     pa.imex = 1;
     pa.im = *imex;
@@ -1272,6 +1309,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fa.dv = p->dv;
       for (int i = 0; i < 25; ++i) fa.ginv[i] = p->ginv[i];
       fa.q = static_cast<double*>(q);
+      fa.status = reinterpret_cast<int32_t*>(ws + lay.status_off);
       if (imex && fa.fuse_project) {
         fa.imex = 1;
         fa.im = *imex;

@@ -330,7 +330,7 @@ void layout(bz_plan* p) {
   p->ws.y_cell = fused ? 0 : align256(n3 * 2 * es * (p->fp32 ? 2 : 1));
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
-  p->ws_fixed = 0;
+  p->ws_fixed = kStatusBytes;  // the numeric status word of the plan's evaluations
   if (p->pad) {
     // forward at n (fhat, scratch), f and raw Q on the padded grid, padded spectrum,
     // Q resampled back (accumulator region), and the padded plan's own workspace
@@ -341,6 +341,7 @@ void layout(bz_plan* p) {
     p->ws.qp_cell = align256(np3 * es);
     p->ws.gp_cell = align256(np3 * 2 * es);
     p->ws.pad_cell = p->pad->ws_per_cell;
+    p->ws_fixed += p->pad->ws_fixed;  // the padded plan's own fixed region sits with its cells
     p->tables_bytes = p->pad->tables_bytes;  // the device tables are the padded operator's
   }
   p->ws_per_cell = p->ws.fh_cell + p->ws.y_cell + p->ws.acc_cell + p->ws.par_cell + p->ws.fp_cell +
@@ -357,14 +358,15 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
   const size_t cap = ws_bytes >= p->ws_fixed + p->ws_per_cell ? (ws_bytes - p->ws_fixed) / p->ws_per_cell : 0;
   b.capacity = int(std::min<size_t>(cap, size_t(1) << 30));
   b.lay = p->ws;
-  b.lay.fh_off = p->ws_fixed;
+  b.lay.status_off = 0;
+  b.lay.fh_off = kStatusBytes;
   b.lay.y_off = b.lay.fh_off + size_t(b.capacity) * b.lay.fh_cell;
   b.lay.acc_off = b.lay.y_off + size_t(b.capacity) * b.lay.y_cell;
   b.lay.par_off = b.lay.acc_off + size_t(b.capacity) * b.lay.acc_cell;
   b.lay.fp_off = b.lay.par_off + size_t(b.capacity) * b.lay.par_cell;
   b.lay.qp_off = b.lay.fp_off + size_t(b.capacity) * b.lay.fp_cell;
   b.lay.gp_off = b.lay.qp_off + size_t(b.capacity) * b.lay.qp_cell;
-  b.lay.pad_off = b.lay.gp_off + size_t(b.capacity) * b.lay.gp_cell;
+  b.lay.pad_off = b.lay.gp_off + size_t(b.capacity) * b.lay.gp_cell;  // padded plan: fixed part, then cells
   return b;
 }
 
@@ -545,11 +547,32 @@ bz_status bz_plan_bind(bz_plan* p, void* tables_dev, void* ws_dev, size_t ws_byt
   const bz_status st = upload_tables(p, tables_dev, static_cast<hipStream_t>(stream));
   if (st != BZ_OK) return st;
   const Binding b = make_binding(p, tables_dev, ws_dev, ws_bytes);
+  static const int32_t kZero = 0;
+  if (hipMemcpy(static_cast<char*>(ws_dev) + b.lay.status_off, &kZero, sizeof(kZero), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(BZ_ERR_DEVICE, "bz_plan_bind: clearing the status word failed");
   p->capacity = b.capacity;
   p->ws = b.lay;
   p->tables_dev = tables_dev;
   p->ws_dev = ws_dev;
   p->ws_bytes = ws_bytes;
+  return BZ_OK;
+}
+
+bz_status bz_plan_sync(bz_plan* p, void* stream) {
+  clear_error();
+  if (!p) return fail(BZ_ERR_ARG, "bz_plan_sync: null plan");
+  if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_plan_sync: plan not bound");
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(BZ_ERR_DEVICE, "bz_plan_sync: stream synchronisation failed");
+  int32_t h = 0;
+  char* w = static_cast<char*>(p->ws_dev) + p->ws.status_off;
+  if (hipMemcpy(&h, w, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(BZ_ERR_DEVICE, "bz_plan_sync: reading the status word failed");
+  if (h != 0) {
+    static const int32_t kZero = 0;
+    (void)hipMemcpy(w, &kZero, sizeof(kZero), hipMemcpyHostToDevice);
+    return fail(BZ_ERR_NUMERIC, "bz_plan_sync: non-finite values in the output of an evaluation since the last sync");
+  }
   return BZ_OK;
 }
 

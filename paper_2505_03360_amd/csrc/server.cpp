@@ -135,6 +135,7 @@ struct Req {
   CachedPlan* cp = nullptr;
   size_t ws_off = 0, ws_bytes = 0;
   hipEvent_t ev = nullptr;
+  int slot = -1;  // pinned host word that receives the request's numeric status
 };
 
 }  // namespace
@@ -146,6 +147,8 @@ struct bz_server {
   std::vector<hipStream_t> streams;
   hipStream_t upload = nullptr;
   std::vector<hipEvent_t> event_pool;
+  int32_t* status_host = nullptr;  // pinned, one word per in-flight slot
+  std::vector<int> free_slots;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<uint64_t> queue;
@@ -266,8 +269,12 @@ void reap(bz_server* s) {
     q.cp->inflight -= 1;
     s->event_pool.push_back(q.ev);
     q.ev = nullptr;
-    if (e == hipSuccess) finish(s, q, BZ_REQ_DONE, BZ_OK);
-    else finish(s, q, BZ_REQ_FAILED, BZ_ERR_DEVICE);
+    const bool nonfinite = q.slot >= 0 && s->status_host[q.slot] != 0;
+    if (q.slot >= 0) s->free_slots.push_back(q.slot);
+    q.slot = -1;
+    if (e != hipSuccess) finish(s, q, BZ_REQ_FAILED, BZ_ERR_DEVICE);
+    else if (nonfinite) finish(s, q, BZ_REQ_FAILED, BZ_ERR_NUMERIC);
+    else finish(s, q, BZ_REQ_DONE, BZ_OK);
     s->inflight[i] = s->inflight.back();
     s->inflight.pop_back();
   }
@@ -308,17 +315,28 @@ void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
     s->next_stream = (s->next_stream + 1) % int(s->streams.size());
     const bz::Binding b = bz::make_binding(p, s->arena.base + cp->tables_off, s->arena.base + off, ws);
     bz_status lst = ev ? BZ_OK : BZ_ERR_DEVICE;
-    if (lst == BZ_OK && q.r.ncells > 0)
+    const int slot = s->free_slots.back();  // at most max_inflight requests are in flight
+    s->free_slots.pop_back();
+    s->status_host[slot] = 0;
+    if (lst == BZ_OK && q.r.ncells > 0) {
+      bz::launch_clear_status(b.ws, b.lay, st);
       lst = bz::launch_collide(p, b, q.r.f, q.r.f_dtype == BZ_FP32, q.r.idx, q.r.ncells, nullptr, q.r.q,
                                (q.r.flags & BZ_SCATTER) != 0, st, false);
+      if (lst == BZ_OK &&
+          hipMemcpyAsync(&s->status_host[slot], static_cast<char*>(b.ws) + b.lay.status_off, sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st) != hipSuccess)
+        lst = BZ_ERR_DEVICE;
+    }
     if (lst == BZ_OK && hipEventRecord(ev, st) != hipSuccess) lst = BZ_ERR_DEVICE;
     s->queue.erase(s->queue.begin() + long(qi));
     if (lst != BZ_OK) {
       s->arena.release(off, ws);
       if (ev) s->event_pool.push_back(ev);
+      s->free_slots.push_back(slot);
       finish(s, q, BZ_REQ_FAILED, lst);
       continue;
     }
+    q.slot = slot;
     q.state = BZ_REQ_ADMITTED;
     q.t_admit = now_ns();
     q.cp = cp;
@@ -374,6 +392,13 @@ bz_status bz_server_create(const bz_server_desc* d, bz_server** out) {
     if (i < d->n_streams) s->streams.push_back(st);
     else s->upload = st;
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->status_host), sizeof(int32_t) * size_t(d->max_inflight),
+                    hipHostMallocDefault) != hipSuccess) {
+    for (auto x : s->streams) (void)hipStreamDestroy(x);
+    if (s->upload) (void)hipStreamDestroy(s->upload);
+    return bz::fail(BZ_ERR_DEVICE, "bz_server_create: pinned status buffer");
+  }
+  for (int i = d->max_inflight - 1; i >= 0; --i) s->free_slots.push_back(i);
   bz_server* raw = s.release();
   raw->th = std::thread(scheduler, raw);
   *out = raw;
@@ -466,6 +491,7 @@ bz_status bz_server_destroy(bz_server* s) {
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
   if (s->upload) (void)hipStreamDestroy(s->upload);
+  if (s->status_host) (void)hipHostFree(s->status_host);
   delete s;
   return BZ_OK;
 }

@@ -185,3 +185,25 @@ def test_timing_and_errors():
     with pytest.raises(bz.BzError) as e:
         col(torch.cat([f, f]))  # 8 cells > capacity 4
     assert e.value.code == bz.BZ_ERR_NOMEM
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_nonfinite_input_reported_by_sync(prec):
+    import paper_2505_03360_amd as bz
+    print("case numeric status", prec, flush=True)
+    n = 16
+    f = torch.from_numpy(gen.shock_batch(3, n, 8.0, seed=9)).cuda()
+    col = bz.Collider(n, 3, L=8.0, m=6, dir_kind=bz.BZ_DIRS_ICOSA6,
+                      precision=bz.BZ_FP32 if prec == "fp32" else bz.BZ_FP64)
+    col(f)
+    bz.bz_plan_sync(col.plan)  # finite: no error
+    g = f.clone()
+    g[2, 3, 4, 5] = float("nan")
+    col(g)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_sync(col.plan)
+    assert e.value.code == bz.BZ_ERR_NUMERIC
+    bz.bz_plan_sync(col.plan)  # the flag was cleared
+    col(f)
+    bz.bz_plan_sync(col.plan)
+    col.close()

@@ -126,3 +126,24 @@ def test_failed_requests_are_isolated():
     st = srv.stats()
     assert st.failed == 2 and st.completed == 1
     srv.close()
+
+
+def test_nonfinite_output_fails_only_its_request():
+    import paper_2505_03360_amd as bz
+    print("case serve nonfinite", flush=True)
+    srv = bz.Server(arena_bytes=1 << 30, max_inflight=4, n_streams=2)
+    good = inputs(16, 3, 21)
+    bad = inputs(16, 3, 22)
+    bad[1, 5, 6, 7] = float("nan")
+    qg = torch.empty((3, 16, 16, 16), dtype=torch.float64, device="cuda")
+    qb = torch.empty_like(qg)
+    tb = srv.submit(bad, qb, plan(bz, 16))
+    tg = srv.submit(good, qg, plan(bz, 16))
+    rb, rg = wait(srv, tb), wait(srv, tg)
+    assert rb.state == bz.BZ_REQ_FAILED and rb.err == bz.BZ_ERR_NUMERIC
+    assert rg.state == bz.BZ_REQ_DONE and rg.err == 0
+    # the next request on the same cached plan and arena starts clean
+    t2 = srv.submit(good, qg, plan(bz, 16))
+    r2 = wait(srv, t2)
+    assert r2.state == bz.BZ_REQ_DONE and r2.err == 0
+    srv.close()
