@@ -460,7 +460,8 @@ bz_status bz_server_destroy(bz_server* server);
 
 /*
  * One time step of the hot path captured as a HIP graph (built once, replayed
- * every step): bz_realizability_mask on the macro fields, then
+ * every step): optionally the kinetic cells' moments from f (below), then
+ * bz_realizability_mask on the macro fields, then
  * bz_collide_batch over the regime-2 cells it lists (count read on the GPU,
  * output scattered to rows boltz_idx of q, FP64 projected), then regime_out
  * copied over regime_in so that the next replay continues from the new
@@ -481,6 +482,16 @@ typedef struct {
   const void* f;                         /* [nx*ny][n][n][n], f_dtype */
   int32_t f_dtype;
   double* q;                             /* [nx*ny][n][n][n] FP64; only rows listed are written */
+  /* Optional first stage (kinetic_moments != 0): the cells whose regime_in is
+     1 or 2 (the kinetic layers, whose f is resident) are listed in kin_idx
+     (ascending, count in kin_count[0]) and get rho, ux, uy, T and l1dist
+     recomputed from f on the plan's velocity grid (bz_cell_moments), so the
+     mask's 1 -> 0 switch sees each kinetic cell's own distance to
+     equilibrium; those five arrays are then written by the replay (l1dist
+     must be given).  Fluid cells keep the caller's fields. */
+  int32_t kinetic_moments;
+  int32_t* kin_idx;                      /* [nx*ny] */
+  int32_t* kin_count;                    /* [1] */
 } bz_step_buffers;
 
 bz_status bz_step_create(const bz_plan* plan, const bz_mask_desc* mask, const bz_step_buffers* bufs,

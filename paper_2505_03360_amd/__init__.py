@@ -92,7 +92,8 @@ class BzStepBuffers(ctypes.Structure):
                 ("T", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("regime_in", ctypes.c_void_p),
                 ("l1dist", ctypes.c_void_p), ("cell_flags", ctypes.c_void_p), ("regime_out", ctypes.c_void_p),
                 ("boltz_idx", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("diag", ctypes.c_void_p),
-                ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32), ("q", ctypes.c_void_p)]
+                ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32), ("q", ctypes.c_void_p),
+                ("kinetic_moments", ctypes.c_int32), ("kin_idx", ctypes.c_void_p), ("kin_count", ctypes.c_void_p)]
 
 
 class BzMomentsOut(ctypes.Structure):

@@ -115,10 +115,11 @@ __global__ __launch_bounds__(256) void k_mask(MaskArgs a) {
   }
 }
 
-// Ascending list of the regime-2 cells: one workgroup sweeps the grid in tiles
-// of 1024 cells; wave ballots give each flagged cell its rank within the tile.
+// Ascending list of the regime-2 cells (kinetic = 0) or of the kinetic cells,
+// regime 1 or 2 (kinetic = 1): one workgroup sweeps the grid in tiles of 1024
+// cells; wave ballots give each flagged cell its rank within the tile.
 __global__ __launch_bounds__(1024) void k_compact(const uint8_t* reg, int ncell, int32_t* idx,
-                                                  int32_t* counts) {
+                                                  int32_t* counts, int kinetic) {
   __shared__ int wsum[16];
   __shared__ int base_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(1024) void k_compact(const uint8_t* reg, int ncell,
   __syncthreads();
   for (int b = 0; b < ncell; b += 1024) {
     const int i = b + t;
-    const bool flag = i < ncell && reg[i] == 2;
+    const bool flag = i < ncell && (reg[i] == 2 || (kinetic && reg[i] == 1));
     const unsigned long long m = __ballot(flag);
     const int pre = __popcll(m & ((1ull << lane) - 1ull));
     if (lane == 0) wsum[wv] = __popcll(m);
@@ -155,6 +156,10 @@ __global__ void k_copy_u8(const uint8_t* src, uint8_t* dst, int n) {
 namespace bz {
 void launch_copy_u8(const uint8_t* src, uint8_t* dst, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_u8, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_compact_kinetic(const uint8_t* regime, int ncell, int32_t* idx, int32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, regime, ncell, idx, count, 1);
 }
 }  // namespace bz
 
@@ -199,7 +204,7 @@ extern "C" bz_status bz_realizability_mask(const bz_mask_desc* d, const double* 
   const int ncell = d->nx * d->ny;
   hipLaunchKernelGGL(k_mask_init, dim3(1), dim3(64), 0, s, counts);
   hipLaunchKernelGGL(k_mask, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, regime_out, ncell, boltz_idx, counts);
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, regime_out, ncell, boltz_idx, counts, 0);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_realizability_mask: launch failed: %s", hipGetErrorString(e));
   return BZ_OK;

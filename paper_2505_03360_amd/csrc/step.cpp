@@ -8,6 +8,7 @@
 
 namespace bz {
 void launch_copy_u8(const uint8_t* src, uint8_t* dst, int n, hipStream_t s);
+void launch_compact_kinetic(const uint8_t* regime, int ncell, int32_t* idx, int32_t* count, hipStream_t s);
 }
 
 struct bz_step {
@@ -31,6 +32,8 @@ bz_status bz_step_create(const bz_plan* plan, const bz_mask_desc* mask, const bz
     return bz::fail(BZ_ERR_ARG, "bz_step_create: null buffer");
   if (b->f_dtype != BZ_FP32 && b->f_dtype != BZ_FP64) return bz::fail(BZ_ERR_ARG, "bz_step_create: bad f_dtype");
   if (!plan->project) return bz::fail(BZ_ERR_ARG, "bz_step_create: the step writes FP64 projected output");
+  if (b->kinetic_moments && (!b->kin_idx || !b->kin_count || !b->l1dist || !b->rho || !b->ux || !b->uy || !b->T))
+    return bz::fail(BZ_ERR_ARG, "bz_step_create: kinetic_moments needs kin_idx, kin_count, l1dist and the fields");
   bz_step* st = new bz_step();
   hipError_t e = hipStreamCreateWithFlags(&st->capture, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -46,7 +49,17 @@ bz_status bz_step_create(const bz_plan* plan, const bz_mask_desc* mask, const bz
   };
   e = hipStreamBeginCapture(st->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return cleanup(BZ_ERR_DEVICE, "begin capture", e);
-  bz_status rc = bz_realizability_mask(mask, b->rho, b->ux, b->uy, b->T, b->eps, b->regime_in, b->l1dist,
+  bz_status rc = BZ_OK;
+  if (b->kinetic_moments) {
+    // the kinetic cells' fields and L1 distance from their own f
+    bz::launch_compact_kinetic(b->regime_in, int(ncell), b->kin_idx, b->kin_count, st->capture);
+    bz_moments_out mo{const_cast<double*>(b->rho), const_cast<double*>(b->ux), const_cast<double*>(b->uy), nullptr,
+                      const_cast<double*>(b->T), const_cast<double*>(b->l1dist)};
+    rc = bz_cell_moments(plan->n, plan->L, b->f, b->f_dtype, b->kin_idx, int(ncell), b->kin_count, &mo, BZ_SCATTER,
+                         st->capture);
+  }
+  if (rc == BZ_OK)
+    rc = bz_realizability_mask(mask, b->rho, b->ux, b->uy, b->T, b->eps, b->regime_in, b->l1dist,
                                        b->cell_flags, b->regime_out, b->boltz_idx, b->counts, b->diag,
                                        st->capture);
   if (rc == BZ_OK) {

@@ -75,3 +75,89 @@ def test_graph_step_replays_match_eager():
         assert np.array_equal(reg_graph.cpu().numpy(), o_out)
         o_reg = o_out
     bz.bz_step_destroy(step)
+
+
+def test_graph_step_with_kinetic_moments():
+    # the captured step first recomputes the kinetic cells' fields and L1 distance from f
+    import math
+
+    import paper_2505_03360_amd as bz
+    from oracle import kinetic
+    print("case graph step kinetic moments", flush=True)
+    nx = ny = 24
+    ncell = nx * ny
+    n, L = 16, 8.0
+    X, Y = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny, indexing="xy")
+    rho = 1.0 + 0.05 * np.sin(2 * math.pi * X)
+    T = 1.0 + 0.05 * np.cos(2 * math.pi * Y)
+    ux = 0.1 * np.sin(2 * math.pi * Y)
+    uy = 0.05 * np.cos(2 * math.pi * X)
+    v = (np.arange(n) - n // 2) * (2 * L / n)
+    V1, V2, V3 = np.meshgrid(v, v, v, indexing="ij")
+    f = np.empty((ncell, n, n, n))
+    for iy in range(ny):
+        for ix in range(nx):
+            u = [ux[iy, ix], uy[iy, ix], 0.0]
+            a = 0.05 if ix >= nx // 2 else 0.0
+            f[iy * nx + ix] = kinetic.maxwellian(rho[iy, ix], u, T[iy, ix], n, L) * \
+                (1.0 + a * (V1 - u[0]) * (V2 - u[1]) / T[iy, ix])
+    cu = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    # the caller's fields are deliberately off for the kinetic cells: the step recomputes them
+    fields_graph = [cu(x * 1.01) for x in (rho, ux, uy, T)]
+    l1_graph = torch.full((ny, nx), 1.0, dtype=torch.float64, device="cuda")
+    fields_eager = [t.clone() for t in fields_graph]
+    l1_eager = l1_graph.clone()
+    eps = torch.full((ny, nx), 1e-4, dtype=torch.float64, device="cuda")
+    reg0 = np.ones((ny, nx), np.uint8)
+    reg0[:, :3] = 0  # a fluid strip keeps the caller's fields
+    reg0[5:8, 15:18] = 2
+    reg_graph, reg_eager = cu(reg0, torch.uint8), cu(reg0, torch.uint8)
+    flags_np = np.zeros((ny, nx), np.uint8)
+    flags_np[5:8, 15:18] = bz.BZ_CELL_FORCE_BOLTZMANN  # keeps a Boltzmann block for the collision stage
+    flags = cu(flags_np, torch.uint8)
+    reg_out = torch.empty_like(reg_graph)
+    idx = torch.zeros(ncell, dtype=torch.int32, device="cuda")
+    counts = torch.zeros(2, dtype=torch.int32, device="cuda")
+    kin_idx = torch.zeros(ncell, dtype=torch.int32, device="cuda")
+    kin_count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ft = cu(f)
+    q_graph = torch.zeros_like(ft)
+    q_eager = torch.zeros_like(ft)
+    md = bz.mask_desc(nx, ny, 1.0 / nx, 1.0 / ny, eta0=1e-3, eta1=50.0, delta0=1e-3)
+    col = bz.Collider(n, ncell, L=L, m=6, dir_kind=bz.BZ_DIRS_ICOSA6, precision=bz.BZ_FP32)
+    b = bz.BzStepBuffers()
+    b.rho, b.ux, b.uy, b.T = [t.data_ptr() for t in fields_graph]
+    b.eps, b.l1dist, b.cell_flags = eps.data_ptr(), l1_graph.data_ptr(), flags.data_ptr()
+    b.regime_in, b.regime_out = reg_graph.data_ptr(), reg_out.data_ptr()
+    b.boltz_idx, b.counts = idx.data_ptr(), counts.data_ptr()
+    b.f, b.f_dtype, b.q = ft.data_ptr(), bz.BZ_FP64, q_graph.data_ptr()
+    b.kinetic_moments, b.kin_idx, b.kin_count = 1, kin_idx.data_ptr(), kin_count.data_ptr()
+    step = bz.bz_step_create(col.plan, md, b)
+    stream = torch.cuda.current_stream().cuda_stream
+    for k in range(3):
+        # eager reference: moments of the kinetic cells, mask, collision, feedback
+        kin = torch.nonzero((reg_eager.view(-1) == 1) | (reg_eager.view(-1) == 2)).view(-1).int()
+        out = dict(zip(("rho", "u1", "u2", "T"), [t.view(-1) for t in fields_eager]))
+        out["l1"] = l1_eager.view(-1)
+        if kin.numel():
+            bz.cell_moments(ft, L, idx=kin, out=out, scatter=True)
+        r2, i2, c2, _ = bz.realizability_mask(md, *fields_eager, eps, reg_eager, l1dist=l1_eager, cell_flags=flags)
+        torch.cuda.synchronize()
+        cnt = int(c2[0])
+        assert cnt == 9
+        if cnt:
+            col(ft, idx=i2[:cnt].contiguous(), out=q_eager, scatter=True)
+        reg_eager.copy_(r2)
+        bz.bz_step_launch(step, stream)
+        torch.cuda.synchronize()
+        assert int(kin_count[0]) == kin.numel() and torch.equal(kin_idx[:kin.numel()], kin)
+        for a, e in zip(fields_graph + [l1_graph], fields_eager + [l1_eager]):
+            assert torch.equal(a, e)
+        assert torch.equal(reg_graph, reg_eager)
+        rows = i2[:cnt].long()
+        assert torch.equal(q_graph[rows], q_eager[rows])
+    # the fluid strip kept the caller's fields; near-equilibrium kinetic cells went to the fluid layer
+    assert torch.equal(fields_graph[0][:, :3], cu(rho * 1.01)[:, :3])
+    final = reg_graph.cpu().numpy()
+    assert (final[:, 3: nx // 2] == 0).any() and (final[:, nx // 2:] >= 1).all()
+    bz.bz_step_destroy(step)
