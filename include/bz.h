@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define BZ_ABI_VERSION 1
+#define BZ_ABI_VERSION 2
 
 typedef int32_t bz_status;
 

@@ -115,6 +115,7 @@ class BzError(RuntimeError):
 
 
 _LIB = None
+ABI_VERSION = 2  # the struct layouts below match include/bz.h at this version
 
 # (name, restype, argtypes) for every symbol declared in include/bz.h
 _VP = ctypes.c_void_p
@@ -176,6 +177,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.bz_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.bz_abi_version()}, the binding expects {ABI_VERSION}: "
+                               "rebuild it with __graft_entry__.build()")
         _LIB = L
     return _LIB
 

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     assert "bz_collide_batch" in syms and "bz_realizability_mask" in syms
     for s in sorted(syms):
         assert hasattr(L, s), s
-    assert bz.bz_abi_version() == 1
+    assert bz.bz_abi_version() == bz.ABI_VERSION
     declared = {name for name, _, _ in bz.SIGNATURES}
     assert syms <= declared | {"bz_serve_submit", "bz_serve_poll", "bz_server_create",
                                "bz_server_destroy", "bz_server_stats"} or syms <= declared
