@@ -262,7 +262,7 @@ def collide_dealiased(f: np.ndarray, plan: Plan, op=None) -> np.ndarray:
     return q.real
 
 
-def collide_fft(f: np.ndarray, plan: Plan) -> np.ndarray:
+def collide_fft(f: np.ndarray, plan: Plan, parts: bool = False):
     """The same operator with library FFTs for the transforms (the paper's CPU
     evaluation: an FFT per cell and direction).  On the grid v_j = (j - N/2) dv
     the exact transforms are the standard DFT times the phase (-1)^ktilde,
@@ -282,7 +282,10 @@ def collide_fft(f: np.ndarray, plan: Plan) -> np.ndarray:
         a, ap = multipliers(plan, p)
         qplus += plan.weights[p] * inv(a * fh) * inv(ap * fh)
     loss = inv(fh) * inv(bhat_m(plan) * fh)
-    return plan.kernel_c * (qplus - loss)
+    c = plan.kernel_c
+    if parts:  # (Q, Q+, loss) as collide_parts returns them
+        return c * (qplus - loss), c * qplus, c * loss
+    return c * (qplus - loss)
 
 
 def moment_matrix(n: int, L: float) -> np.ndarray:

@@ -207,3 +207,28 @@ def test_nonfinite_input_reported_by_sync(prec):
     col(f)
     bz.bz_plan_sync(col.plan)
     col.close()
+
+
+@pytest.mark.parametrize("n", [32, 48])
+def test_maximum_request_size_sampled(n):
+    # 4096 cells, the largest request of the serving workload: sampled cells against the oracle
+    import paper_2505_03360_amd as bz
+    print("case max size", n, flush=True)
+    cells, L = 4096, 8.0
+    base = gen.shock_batch(16, n, L, seed=50 + n)
+    f = torch.from_numpy(base).cuda().repeat(cells // 16, 1, 1, 1).contiguous()
+    f[cells - 1] = torch.from_numpy(gen.shock_batch(1, n, L, seed=99)[0]).cuda()
+    col = bz.Collider(n, cells, L=L, m=32, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP32)
+    idx = torch.arange(cells - 1, -1, -1, dtype=torch.int32, device="cuda")  # reversed rows, scattered back
+    q = torch.zeros((cells, n, n, n), dtype=torch.float64, device="cuda")
+    col(f, idx=idx, out=q, scatter=True)
+    torch.cuda.synchronize()
+    plan = oracle_plan(n, rule="spiral", m=32)
+    for r in (0, 7, cells - 1):
+        fr = f[r].cpu().numpy()
+        qq, _, loss = spectral.collide_fft(fr, plan, parts=True)
+        err = spectral.rel_err(q[r].cpu().numpy(), spectral.project(qq, n, L), loss)
+        print(f"  row {r}: err {err:.3e}", flush=True)
+        assert err <= 1e-5
+    assert torch.equal(q[0], q[16])  # identical inputs give identical outputs anywhere in the batch
+    col.close()

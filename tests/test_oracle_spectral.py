@@ -286,6 +286,9 @@ def test_fft_mode_equals_the_naive_dft_oracle():
         f = gen.shock_batch(1, n, 8.0, seed=3)[0]
         q = spectral.collide(f, plan)
         assert np.abs(spectral.collide_fft(f, plan) - q).max() <= 1e-12 * np.abs(q).max()
+        parts, ref_parts = spectral.collide_fft(f, plan, parts=True), spectral.collide_parts(f, plan)
+        for a, b in zip(parts, ref_parts):
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
 
 
 # ---------------------------------------------------------------- dealiased variant
