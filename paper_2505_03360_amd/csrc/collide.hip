@@ -19,13 +19,21 @@
 // [k2][k3][k1] (k1 fastest, so that stage-A pencils along k3 are read with
 // consecutive lanes on consecutive k1); acc [j1][j2][j3].
 //
-// Two evaluation strategies share the forward transform and the projection:
-//   plain: three pencil passes per direction through HBM, one thread per
-//          pencil (any n, FP32 or FP64);
-//   fused: one workgroup per (cell, direction chunk) runs every direction of
-//          its chunk on chip: stage-A pencils along k3 in registers, two
-//          transposes through LDS (in j3 slices), stage-C pencils along k1 in
-//          registers, and the products accumulated in registers (FP32).
+// Evaluation strategies (all share the multiplier tables and the projection):
+//   fused (FP32, n = 16 and 32): one forward kernel, then one workgroup per
+//          (cell, direction chunk) runs every direction of its chunk on chip:
+//          stage-A pencils along k3 in registers, a transpose through LDS in
+//          j3 slices, stage-B pencils along k2, a wave-local transpose,
+//          stage-C pencils along k1, products accumulated in registers; the
+//          projection or an IMEX update can run in the same kernel;
+//   chunked plain (FP32 plans that use no fused kernel): the stage-A pass writes K directions'
+//          intermediates at once, a second kernel runs stages B and C with
+//          the B->C transpose in LDS and accumulates over the chunk;
+//   plain (FP64): three pencil passes per direction through HBM, one thread
+//          per pencil;
+//   dealiased (either precision): f is resampled spectrally onto a 3n/2 grid,
+//          the plain or chunked passes run there, and the result is
+//          resampled back onto the n grid.
 #include "bz_internal.hpp"
 #include "fft.hpp"
 #include "kinetic.hpp"
