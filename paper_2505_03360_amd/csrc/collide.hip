@@ -426,8 +426,8 @@ __device__ __forceinline__ void lds_barrier() {
 struct FusedArgs {
   int ncells;
   const int32_t* ncells_dev;
-  const void* f;
-  int f_fp32;
+  const float* fc;    // [cell][slice][j1][thread]: FP32 copy of f in stage-C order (loss pass)
+  size_t fc_stride;
   const int32_t* idx;
   const cx<float>* fh;
   size_t fh_stride;
@@ -459,11 +459,18 @@ struct FwdArgs {
   cx<float>* fh;  // [cell][k2][k3][k1]
   size_t fh_stride;
   int mirror;  // also write rows k2 in (N/2, N) (consumers that read every row)
+  float* fc;   // [cell][slice][j1][t]: FP32 f in the collision kernel's stage-C order
+  size_t fc_stride;
 };
 
 // Forward transform fhat = DFT(f) / N^3 of one cell per workgroup, FP32,
 // N^2/2 threads, everything between the load of f and the write of fhat on
 // chip.
+//   stage 0: f is read once, coalesced, into LDS as FP32 ([i1][i2][i3], row
+//            pitch N + 1), and written back out as fc in the order in which
+//            the collision kernel's threads consume it in the loss pass:
+//            fc[s][j1][t] = f[j1][t % N][s W + t / N] (W = N / S, S the
+//            slices of that kernel), so that those reads are coalesced;
 //   stage 1: thread (i1 < N/2, i3) transforms z(i2) = f[i1][i2][i3] +
 //            i f[i1 + N/2][i2][i3] along i2; f is real, so the two transforms
 //            follow from Z(k2) and conj Z(-k2).  Only k2 in [0, N/2] is kept:
@@ -474,7 +481,7 @@ struct FwdArgs {
 //            written as conj fhat(-k1, k2, -k3).
 // LDS [k2 in 0..N/2][i1, then k1][i3] with row pitch N + 1 (stage 3 reads with
 // lanes on k1 and lands on distinct banks).
-template <int N>
+template <int N, int S>
 __global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
   constexpr int T = N * N / 2, H = N / 2, P = N + 1;
   __shared__ cx<float> lds[(H + 1) * N * P];
@@ -482,19 +489,35 @@ __global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
   if (cell >= live_count(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
   const long row = a.idx ? long(a.idx[cell]) : long(cell);
+  constexpr int N3 = N * N * N;
+  static_assert(N * N * P <= 2 * (H + 1) * N * P, "f fits the LDS as FP32");
+  float* lf = reinterpret_cast<float*>(lds);  // [i1][i2][i3], row pitch P
+  if (a.f_fp32) {
+    const float* f = static_cast<const float*>(a.f) + size_t(row) * N3;
+#pragma unroll 8
+    for (int e = t; e < N3; e += T) lf[(e / N) * P + e % N] = f[e];
+  } else {
+    const double* f = static_cast<const double*>(a.f) + size_t(row) * N3;
+#pragma unroll 8
+    for (int e = t; e < N3; e += T) lf[(e / N) * P + e % N] = float(f[e]);
+  }
+  lds_barrier();
+  {
+    constexpr int W = N / S, TC = N * W;
+    float* fc = a.fc + cell * a.fc_stride;
+#pragma unroll 8
+    for (int o = t; o < N3; o += T) {
+      const int tc = o % TC, j1 = (o / TC) % N, sl = o / (N * TC);
+      const int j2 = tc % N, j3 = sl * W + tc / N;
+      fc[o] = lf[(j1 * N + j2) * P + j3];
+    }
+  }
   {
     const int i3 = t % N, i1 = t / N;
-    const size_t base = size_t(row) * N * N * N + size_t(i1) * N * N + i3;
     cx<float> z[N];
-    if (a.f_fp32) {
-      const float* f = static_cast<const float*>(a.f) + base;
 #pragma unroll
-      for (int i2 = 0; i2 < N; ++i2) z[i2] = {f[i2 * N], f[size_t(H) * N * N + i2 * N]};
-    } else {
-      const double* f = static_cast<const double*>(a.f) + base;
-#pragma unroll
-      for (int i2 = 0; i2 < N; ++i2) z[i2] = {float(f[i2 * N]), float(f[size_t(H) * N * N + i2 * N])};
-    }
+    for (int i2 = 0; i2 < N; ++i2) z[i2] = {lf[(i1 * N + i2) * P + i3], lf[((i1 + H) * N + i2) * P + i3]};
+    lds_barrier();  // every thread has its rows: the LDS is reused below
     bzk::fft<N, -1>(z);
 #pragma unroll
     for (int k2 = 0; k2 <= H; ++k2) {
@@ -554,7 +577,7 @@ __global__ __launch_bounds__(N * N / 2) void k_fwd_fused(FwdArgs a) {
 // data): a wave synchronises only with itself between stages B and C.
 template <int N, int S, bool LOSS>
 __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, const cx<float>* fhc,
-                                           long row, int p, int t, float (&acc)[S][N]) {
+                                           const float* fcc, int p, int t, float (&acc)[S][N]) {
   constexpr int T = N * N / S;
   constexpr int W = N / S;
   constexpr int AB = W + 1;
@@ -714,17 +737,11 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     }
     bzk::fft<N, 1>(rc);
     if constexpr (LOSS) {
-      // acc -= (sL f - Im) Re with the exact input f
-      const size_t fo = size_t(row) * N * N * N + size_t(tk) * N + s * W + tj;
-      if (a.f_fp32) {
-        const float* fp = static_cast<const float*>(a.f) + fo;
+      // acc -= (sL f - Im) Re with the input f, read from the FP32 copy the
+      // forward kernel wrote in this thread's order ([slice][j1][thread])
+      const gptr<float> fp = opaque_global(fcc + size_t(s) * N * T + t);
 #pragma unroll
-        for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * fp[j1 * N * N] - rc[j1].y) * rc[j1].x;
-      } else {
-        const double* fp = static_cast<const double*>(a.f) + fo;
-#pragma unroll
-        for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * float(fp[j1 * N * N]) - rc[j1].y) * rc[j1].x;
-      }
+      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * fp[j1 * T] - rc[j1].y) * rc[j1].x;
     } else {
 #pragma unroll
       for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += wp * rc[j1].x * rc[j1].y;
@@ -767,8 +784,9 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[s][j] = 0.0f;
   const int gain_end = p1 < a.m1 - 1 ? p1 : a.m1 - 1;
-  for (int p = p0; p < gain_end; ++p) fused_pass<N, S, false>(a, lds, fhc, row, p, t, acc);
-  if (p1 == a.m1) fused_pass<N, S, true>(a, lds, fhc, row, a.m1 - 1, t, acc);
+  const float* fcc = a.fc + cell * a.fc_stride;
+  for (int p = p0; p < gain_end; ++p) fused_pass<N, S, false>(a, lds, fhc, fcc, p, t, acc);
+  if (p1 == a.m1) fused_pass<N, S, true>(a, lds, fhc, fcc, a.m1 - 1, t, acc);
   const int j2 = t % N, tl = t / N;  // this thread's stage-C (j2, j3 % W)
   if (a.fuse_project) {
     // Q = C acc; moments m = sum_j (1, v1, v2, v3, |v|^2) Q_j in FP64 with a
@@ -821,21 +839,35 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
     const long orow = a.scatter ? row : long(cell);
     double* q = a.q + size_t(orow) * N * N * N;
     [[maybe_unused]] const double eps_c = IMEX ? (a.im.eps_cells ? a.im.eps_cells[row] : a.im.eps) : 0.0;
+    // Each slice of projected Q goes through LDS ([j1][j2][j3 % W], pitch W + 1
+    // doubles), then the workgroup sweeps it in memory order: the stores (and
+    // the IMEX update's loads of f and v.grad f) cover whole rows of W
+    // consecutive j3 instead of the 16-byte pieces of the stage-C ownership.
+    constexpr int T = N * N / S;
+    constexpr int SP = W + 1;
+    static_assert(sizeof(double) * N * N * SP <= sizeof(cx<float>) * (N * N + N - 1) * AB, "a slice fits the LDS");
+    double* st = reinterpret_cast<double*>(lds);
     bool bad = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const double v3 = (s * W + tl - N / 2) * a.dv;
+      lds_barrier();  // the LDS is free (reduction read, or the previous slice swept)
 #pragma unroll
       for (int j1 = 0; j1 < N; ++j1) {
         const double v1 = (j1 - N / 2) * a.dv;
         const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
-        const size_t e = size_t(j1) * N * N + size_t(j2) * N + s * W + tl;
-        const double qv = a.C * double(acc[s][j1]) - corr;
-        double ov = qv;
+        st[(j1 * N + j2) * SP + tl] = a.C * double(acc[s][j1]) - corr;
+      }
+      lds_barrier();
+#pragma unroll 4
+      for (int o = t; o < N * N * W; o += T) {
+        const int jw = o % W, jj = o / W;  // jj = j1 * N + j2
+        const size_t e = size_t(jj) * N + s * W + jw;
+        double ov = st[jj * SP + jw];
         if constexpr (IMEX) {
           const size_t fe = size_t(row) * N * N * N + e;
-          ov = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c,
-                               a.im.dt, v1, v2, v3);
+          ov = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, ov, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
+                               (jj / N - N / 2) * a.dv, (jj % N - N / 2) * a.dv, (s * W + jw - N / 2) * a.dv);
         }
         q[e] = ov;
         bad |= !isfinite(ov);
@@ -1105,9 +1137,9 @@ bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStre
   return BZ_OK;
 }
 
-template <int N>
+template <int N, int S>
 void launch_fwd_fused(const FwdArgs& a, int ncells, hipStream_t s) {
-  hipLaunchKernelGGL((k_fwd_fused<N>), dim3(unsigned(ncells)), dim3(N * N / 2), 0, s, a);
+  hipLaunchKernelGGL((k_fwd_fused<N, S>), dim3(unsigned(ncells)), dim3(N * N / 2), 0, s, a);
 }
 
 template <int N, int S>
@@ -1293,15 +1325,18 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fw.fh = a.fh;
       fw.fh_stride = a.fh_stride;
       fw.mirror = p->slices == 1 ? 1 : 0;  // the one-slice kernels read every row
-      if (p->n == 32) launch_fwd_fused<32>(fw, ncells, s);
-      else if (p->n == 16) launch_fwd_fused<16>(fw, ncells, s);
+      fw.fc = reinterpret_cast<float*>(ws + lay.y_off);
+      fw.fc_stride = lay.y_cell / sizeof(float);
+      if (p->n == 32) launch_fwd_fused<32, 2>(fw, ncells, s);
+      else if (p->n == 16 && p->slices == 1) launch_fwd_fused<16, 1>(fw, ncells, s);
+      else if (p->n == 16) launch_fwd_fused<16, 2>(fw, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
       if (timed) (void)hipEventRecord(pm->ev[1], s);
       FusedArgs fa{};
       fa.ncells = ncells;
       fa.ncells_dev = ncells_dev;
-      fa.f = f;
-      fa.f_fp32 = f_fp32;
+      fa.fc = fw.fc;
+      fa.fc_stride = fw.fc_stride;
       fa.idx = idx;
       fa.fh = a.fh;
       fa.fh_stride = a.fh_stride;
