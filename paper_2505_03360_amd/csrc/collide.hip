@@ -150,6 +150,23 @@ __device__ __forceinline__ T load_f(const void* f, int f_fp32, size_t i) {
   return f_fp32 ? T(static_cast<const float*>(f)[i]) : T(static_cast<const double*>(f)[i]);
 }
 
+// Global-address-space pointer whose value the compiler cannot see through:
+// per-pass load bases stay in the pass loop (the compiler would otherwise
+// hoist every base + k*stride address out of it, 2 registers each), and the
+// loads remain global (not flat) loads with immediate offsets.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = const T*;
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> opaque_global(const T* p) {
+  asm volatile("" : "+v"(p));
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------------ plain passes
 // pass A: X = (alpha + i alpha') fhat, inverse along k3; thread (cell, k2, k1)
 template <typename T, int N>
@@ -330,7 +347,7 @@ template <int N>
 constexpr int plain_planes_per_wave() { return 64 / N; }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_pBC(PlainArgs<T> a) {
+__global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
   constexpr int PL = plain_planes_per_wave<N>();  // planes per wave
   constexpr int PW = 4 * PL;                      // planes per workgroup
   constexpr int NG = N / PW;                      // workgroups per cell
@@ -348,15 +365,16 @@ __global__ __launch_bounds__(256) void k_pBC(PlainArgs<T> a) {
 #pragma unroll
   for (int j1 = 0; j1 < N; ++j1) accr[j1] = (act && !a.first) ? acc[size_t(j1) * N + k] : T(0);
   const long row = a.idx ? long(a.idx[c]) : long(c);
+#pragma unroll 1
   for (int d = 0; d < kPlainChunk; ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const T wp = a.w[p];
     if (act) {
-      const cx<T>* y = a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(j3) * N * N + k;
+      const gptr<cx<T>> y = opaque_global(a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(j3) * N * N + k);
       cx<T> x[N];
 #pragma unroll
-      for (int k2 = 0; k2 < N; ++k2) x[k2] = y[size_t(k2) * N];
+      for (int k2 = 0; k2 < N; ++k2) x[k2] = y[k2 * N];
       bzk::fft<N, 1>(x);
 #pragma unroll
       for (int j2 = 0; j2 < N; ++j2) tr[pl][j2][k] = x[j2];
@@ -373,9 +391,15 @@ __global__ __launch_bounds__(256) void k_pBC(PlainArgs<T> a) {
       if (p == a.m1 - 1) {
         // loss pass: acc -= (sL f - Im) Re with the exact input f at (j1, j2 = k, j3)
         const size_t fb = size_t(row) * N * N * N + size_t(k) * N + j3;
+        if (a.f_fp32) {
+          const gptr<float> fp = opaque_global(static_cast<const float*>(a.f) + fb);
 #pragma unroll
-        for (int j1 = 0; j1 < N; ++j1)
-          accr[j1] -= (wp * load_f<T>(a.f, a.f_fp32, fb + size_t(j1) * N * N) - x[j1].y) * x[j1].x;
+          for (int j1 = 0; j1 < N; ++j1) accr[j1] -= (wp * T(fp[j1 * N * N]) - x[j1].y) * x[j1].x;
+        } else {
+          const gptr<double> fp = opaque_global(static_cast<const double*>(a.f) + fb);
+#pragma unroll
+          for (int j1 = 0; j1 < N; ++j1) accr[j1] -= (wp * T(fp[j1 * N * N]) - x[j1].y) * x[j1].x;
+        }
       } else {
 #pragma unroll
         for (int j1 = 0; j1 < N; ++j1) accr[j1] += wp * x[j1].x * x[j1].y;
@@ -389,22 +413,6 @@ __global__ __launch_bounds__(256) void k_pBC(PlainArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ fused FP32
-// Global-address-space pointer whose value the compiler cannot see through:
-// per-pass load bases stay in the pass loop (the compiler would otherwise
-// hoist every base + k*stride address out of it, 2 registers each), and the
-// loads remain global (not flat) loads with immediate offsets.
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-using gptr = const __attribute__((address_space(1))) T*;
-#else
-template <typename T>
-using gptr = const T*;
-#endif
-template <typename T>
-__device__ __forceinline__ gptr<T> opaque_global(const T* p) {
-  asm volatile("" : "+v"(p));
-  return (gptr<T>)p;
-}
 
 // Workgroup barrier that orders LDS traffic only: global loads issued before
 // it stay in flight (a full __syncthreads would wait for them).
