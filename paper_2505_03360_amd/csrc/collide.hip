@@ -821,21 +821,23 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) m[k] += __shfl_xor(m[k], o);
     constexpr int NW = (N * N / S) / 64;
-    double* red = reinterpret_cast<double*>(lds);
+    double* red = reinterpret_cast<double*>(lds);  // [k][wave] partials, then the 5 totals
     lds_barrier();  // the last pass's stage C has read the LDS
     if ((t & 63) == 0)
 #pragma unroll
       for (int k = 0; k < 5; ++k) red[k * NW + t / 64] = m[k];
     lds_barrier();
+    if (t < 5) {
+      double x = 0.0;
+      for (int wv = 0; wv < NW; ++wv) x += red[t * NW + wv];
+      red[5 * NW + t] = x;
+    }
+    lds_barrier();
     double lam[5];
     {
       double tot[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        double x = 0.0;
-        for (int wv = 0; wv < NW; ++wv) x += red[k * NW + wv];
-        tot[k] = x;
-      }
+      for (int k = 0; k < 5; ++k) tot[k] = red[5 * NW + k];
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         double x = 0.0;
@@ -893,7 +895,6 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
 
 // ------------------------------------------------------------------ projection
 struct ProjArgs {
-  int n;
   int ncells;
   const int32_t* ncells_dev;
   const int32_t* idx;
@@ -917,87 +918,89 @@ __device__ __forceinline__ double load_acc(const ProjArgs& a, size_t i) {
   return a.acc_fp32 ? double(static_cast<const float*>(a.acc)[i]) : static_cast<const double*>(a.acc)[i];
 }
 
+constexpr int kProjThreads = 1024;
+constexpr int kProjWaves = kProjThreads / 64;
+
+// Sum of five per-thread FP64 values over the workgroup in a fixed order
+// (across each wave, then wave by wave); every thread gets the totals.
+// red holds 5 * (kProjWaves + 1) doubles.
+__device__ __forceinline__ void proj_sum5(double (&m)[5], double* red) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m[k] += __shfl_xor(m[k], o);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k * kProjWaves + wv] = m[k];
+  __syncthreads();
+  if (t < 5) {
+    double x = red[t * kProjWaves];
+    for (int w = 1; w < kProjWaves; ++w) x += red[t * kProjWaves + w];
+    red[5 * kProjWaves + t] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 5; ++k) m[k] = red[5 * kProjWaves + k];
+}
+
+__device__ __forceinline__ void proj_lambda(const ProjArgs& a, const double (&tot)[5], double (&lam)[5]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) x += a.ginv[5 * i + k] * tot[k];
+    lam[i] = x;
+  }
+}
+
 // One workgroup per cell.  qr_j = C * sum_chunks acc; moments m = C qr
 // (1, v1, v2, v3, |v|^2) reduced in a fixed order; lambda = G^-1 m;
 // q_j = qr_j - (l0 + l1 v1 + l2 v2 + l3 v3 + l4 |v|^2).
-__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+template <int N>
+__global__ __launch_bounds__(kProjThreads) void k_project(ProjArgs a) {
+  constexpr int N3 = N * N * N;
   const int c = blockIdx.x;
   if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const int n = a.n;
-  const size_t n3 = size_t(n) * n * n;
   const size_t base = size_t(c) * a.acc_stride;
   const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
   const size_t frow = a.idx ? size_t(a.idx[c]) : size_t(c);  // row of the input f
   const int t = threadIdx.x;
-  auto qraw = [&](size_t j) {
+  auto qraw = [&](int j) {
     double s = 0.0;
-    for (int ch = 0; ch < a.chunks; ++ch) s += load_acc(a, base + size_t(ch) * n3 + j);
+    for (int ch = 0; ch < a.chunks; ++ch) s += load_acc(a, base + size_t(ch) * N3 + j);
     return a.C * s;
   };
   const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
-  auto imex_out = [&](size_t j, double qv) {
-    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
-    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
-    const size_t fe = frow * n3 + j;
-    return bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
-                           v1, v2, v3);
-  };
+  double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (a.project) {
+    __shared__ double red[5 * (kProjWaves + 1)];
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int j = t; j < N3; j += kProjThreads) {
+      const double v1 = (j / (N * N) - N / 2) * a.dv, v2 = ((j / N) % N - N / 2) * a.dv, v3 = (j % N - N / 2) * a.dv;
+      const double qv = qraw(j);
+      m[0] += qv;
+      m[1] += v1 * qv;
+      m[2] += v2 * qv;
+      m[3] += v3 * qv;
+      m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
+    }
+    proj_sum5(m, red);
+    proj_lambda(a, m, lam);
+  }
   bool bad = false;
-  if (!a.project && a.imex) {
-    for (size_t j = t; j < n3; j += blockDim.x) {
-      const double v = imex_out(j, qraw(j));
-      static_cast<double*>(a.q)[row * n3 + j] = v;
-      bad |= !isfinite(v);
+#pragma unroll 4
+  for (int j = t; j < N3; j += kProjThreads) {
+    const double v1 = (j / (N * N) - N / 2) * a.dv, v2 = ((j / N) % N - N / 2) * a.dv, v3 = (j % N - N / 2) * a.dv;
+    double v = qraw(j);
+    if (a.project) v -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
+    if (a.imex) {
+      const size_t fe = frow * N3 + j;
+      v = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, v, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt, v1, v2, v3);
     }
-    flag_nonfinite(a.status, a.zero, bad);
-    return;
-  }
-  if (!a.project) {
-    for (size_t j = t; j < n3; j += blockDim.x) {
-      const double v = qraw(j);
-      if (a.q_fp32) static_cast<float*>(a.q)[row * n3 + j] = float(v);
-      else static_cast<double*>(a.q)[row * n3 + j] = v;
-      bad |= !isfinite(v);
-    }
-    flag_nonfinite(a.status, a.zero, bad);
-    return;
-  }
-  double m[5] = {0, 0, 0, 0, 0};
-  for (size_t j = t; j < n3; j += blockDim.x) {
-    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
-    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
-    const double qv = qraw(j);
-    m[0] += qv;
-    m[1] += v1 * qv;
-    m[2] += v2 * qv;
-    m[3] += v3 * qv;
-    m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
-  }
-  __shared__ double red[5][256];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) red[k][t] = m[k];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h)
-#pragma unroll
-      for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + h];
-    __syncthreads();
-  }
-  double lam[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) s += a.ginv[5 * i + k] * red[k][0];
-    lam[i] = s;
-  }
-  double* q = static_cast<double*>(a.q) + row * n3;
-  for (size_t j = t; j < n3; j += blockDim.x) {
-    const int i1 = int(j / (size_t(n) * n)), i2 = int((j / n) % n), i3 = int(j % n);
-    const double v1 = (i1 - n / 2) * a.dv, v2 = (i2 - n / 2) * a.dv, v3 = (i3 - n / 2) * a.dv;
-    const double corr = lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
-    const double v = a.imex ? imex_out(j, qraw(j) - corr) : qraw(j) - corr;
-    q[j] = v;
+    if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * N3 + j] = v;
+    else static_cast<float*>(a.q)[row * N3 + j] = float(v);
     bad |= !isfinite(v);
   }
   flag_nonfinite(a.status, a.zero, bad);
@@ -1006,25 +1009,27 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
 // Projection of a plane-major accumulator acc[cell][j3][j1][j2] (one chunk,
 // FP32, from the chunked plain passes).  Moments are summed in the
 // accumulator's own order (fixed); the output [j1][j2][j3] is written through
-// LDS tiles of 32 (j1, j2) columns so that both the reads and the writes are
+// LDS tiles of 64 (j1, j2) columns so that both the reads and the writes are
 // coalesced.
-__global__ __launch_bounds__(256) void k_project_pm(ProjArgs a) {
+template <int N>
+__global__ __launch_bounds__(kProjThreads) void k_project_pm(ProjArgs a) {
+  constexpr int N2 = N * N, N3 = N2 * N, TC = 64;
+  static_assert(N2 % TC == 0, "column tiles cover the plane");
   const int c = blockIdx.x;
   if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const int n = a.n;
-  const size_t n2 = size_t(n) * n, n3 = n2 * n;
   const float* acc = static_cast<const float*>(a.acc) + size_t(c) * a.acc_stride;
   const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
   const size_t frow = a.idx ? size_t(a.idx[c]) : size_t(c);
   const int t = threadIdx.x;
-  __shared__ double red[5][256];
-  __shared__ double tile[48][33];  // [j3][column], n <= 48
+  __shared__ double red[5 * (kProjWaves + 1)];
+  __shared__ double tile[N][TC + 1];  // [j3][column]
   double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (a.project) {
-    double m[5] = {0, 0, 0, 0, 0};
-    for (size_t e = t; e < n3; e += blockDim.x) {
-      const int j3 = int(e / n2), j1 = int((e / n) % n), j2 = int(e % n);
-      const double v1 = (j1 - n / 2) * a.dv, v2 = (j2 - n / 2) * a.dv, v3 = (j3 - n / 2) * a.dv;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int e = t; e < N3; e += kProjThreads) {
+      const int j3 = e / N2, j1 = (e / N) % N, j2 = e % N;
+      const double v1 = (j1 - N / 2) * a.dv, v2 = (j2 - N / 2) * a.dv, v3 = (j3 - N / 2) * a.dv;
       const double qv = a.C * double(acc[e]);
       m[0] += qv;
       m[1] += v1 * qv;
@@ -1032,51 +1037,63 @@ __global__ __launch_bounds__(256) void k_project_pm(ProjArgs a) {
       m[3] += v3 * qv;
       m[4] += (v1 * v1 + v2 * v2 + v3 * v3) * qv;
     }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) red[k][t] = m[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (t < h)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + h];
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      double x = 0.0;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) x += a.ginv[5 * i + k] * red[k][0];
-      lam[i] = x;
-    }
+    proj_sum5(m, red);
+    proj_lambda(a, m, lam);
   }
   const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
   bool bad = false;
-  for (size_t J0 = 0; J0 < n2; J0 += 32) {
+  for (int J0 = 0; J0 < N2; J0 += TC) {
     __syncthreads();  // the previous tile has been written out
-    for (int i = t; i < n * 32; i += blockDim.x) {
-      const int j3 = i / 32, jj = i % 32;
-      tile[j3][jj] = a.C * double(acc[size_t(j3) * n2 + J0 + jj]);
+    for (int i = t; i < N * TC; i += kProjThreads) {
+      const int j3 = i / TC, jj = i % TC;
+      tile[j3][jj] = a.C * double(acc[j3 * N2 + J0 + jj]);
     }
     __syncthreads();
-    for (int i = t; i < 32 * n; i += blockDim.x) {
-      const int jj = i / n, j3 = i % n;
-      const size_t J = J0 + jj;
-      const int j1 = int(J / n), j2 = int(J % n);
-      const size_t j = J * n + j3;  // [j1][j2][j3]
-      const double v1 = (j1 - n / 2) * a.dv, v2 = (j2 - n / 2) * a.dv, v3 = (j3 - n / 2) * a.dv;
+    for (int i = t; i < TC * N; i += kProjThreads) {
+      const int jj = i / N, j3 = i % N;
+      const int J = J0 + jj;
+      const int j1 = J / N, j2 = J % N;
+      const size_t j = size_t(J) * N + j3;  // [j1][j2][j3]
+      const double v1 = (j1 - N / 2) * a.dv, v2 = (j2 - N / 2) * a.dv, v3 = (j3 - N / 2) * a.dv;
       double qv = tile[j3][jj];
       if (a.project) qv -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
       if (a.imex) {
-        const size_t fe = frow * n3 + j;
+        const size_t fe = frow * N3 + j;
         qv = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
                              v1, v2, v3);
       }
-      if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * n3 + j] = qv;
-      else static_cast<float*>(a.q)[row * n3 + j] = float(qv);
+      if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * N3 + j] = qv;
+      else static_cast<float*>(a.q)[row * N3 + j] = float(qv);
       bad |= !isfinite(qv);
     }
   }
   flag_nonfinite(a.status, a.zero, bad);
+}
+
+// Launch the projection of a plan's accumulator (plane-major for the chunked
+// FP32 passes); false for a grid size without an instantiation.
+bool launch_project(int n, bool plane_major, const ProjArgs& pa, int ncells, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(ncells)), block(kProjThreads);
+  switch (n) {
+    case 16:
+      if (plane_major) hipLaunchKernelGGL(k_project_pm<16>, grid, block, 0, s, pa);
+      else hipLaunchKernelGGL(k_project<16>, grid, block, 0, s, pa);
+      return true;
+    case 24:
+      if (plane_major) hipLaunchKernelGGL(k_project_pm<24>, grid, block, 0, s, pa);
+      else hipLaunchKernelGGL(k_project<24>, grid, block, 0, s, pa);
+      return true;
+    case 32:
+      if (plane_major) hipLaunchKernelGGL(k_project_pm<32>, grid, block, 0, s, pa);
+      else hipLaunchKernelGGL(k_project<32>, grid, block, 0, s, pa);
+      return true;
+    case 48:
+      if (plane_major) hipLaunchKernelGGL(k_project_pm<48>, grid, block, 0, s, pa);
+      else hipLaunchKernelGGL(k_project<48>, grid, block, 0, s, pa);
+      return true;
+    default:
+      return false;
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1224,7 +1241,6 @@ bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f
   if (timed) (void)hipEventRecord(pm->ev[2], s);
   // 6. projection / output (the padded Q already carries the kernel constant)
   ProjArgs pa{};
-  pa.n = N;
   pa.ncells = ncells;
   pa.ncells_dev = ncells_dev;
   pa.idx = idx;
@@ -1244,7 +1260,7 @@ bz_status launch_dealiased(const bz_plan* p, const bz::Binding& b, const void* f
     pa.imex = 1;
     pa.im = *imex;
   }
-  hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
+  if (!launch_project(N, false, pa, ncells, s)) return bz::fail(BZ_ERR_UNSUPPORTED, "projection: n=%d", N);
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);
     pm->timed_calls += 1;
@@ -1286,7 +1302,6 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
     (void)hipEventRecord(pm->ev[0], s);
   }
   ProjArgs pa{};
-  pa.n = p->n;
   pa.ncells = ncells;
   pa.ncells_dev = ncells_dev;
   pa.idx = idx;
@@ -1392,12 +1407,8 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   }
   if (st != BZ_OK) return st;
   if (timed) (void)hipEventRecord(pm->ev[2], s);
-  if (!fused_projection) {
-    if (p->fp32 && p->transform == BZ_XF_PLAIN)
-      hipLaunchKernelGGL(k_project_pm, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
-    else
-      hipLaunchKernelGGL(k_project, dim3(unsigned(ncells)), dim3(256), 0, s, pa);
-  }
+  if (!fused_projection && !launch_project(p->n, p->fp32 && p->transform == BZ_XF_PLAIN, pa, ncells, s))
+    return fail(BZ_ERR_UNSUPPORTED, "projection: n=%d", p->n);
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);
     pm->timed_calls += 1;

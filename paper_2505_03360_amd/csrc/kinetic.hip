@@ -29,8 +29,12 @@ __device__ __forceinline__ int live_cells(int ncells, const int32_t* ncells_dev)
 }
 
 // Sum K per-thread values over the workgroup; every thread gets the totals.
+// red holds K * (kWaves + 1) doubles: the per-wave partials, then the totals.
+// Thread k sums the partials of value k over the waves in order (a fixed
+// order), so that no thread holds more than K partials at once.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&m)[K], double* red) {
+  static_assert(K <= kThreads, "one thread per value");
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -40,12 +44,14 @@ __device__ __forceinline__ void block_sum(double (&m)[K], double* red) {
 #pragma unroll
     for (int k = 0; k < K; ++k) red[k * kWaves + wv] = m[k];
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = red[k * kWaves];
-    for (int w = 1; w < kWaves; ++w) x += red[k * kWaves + w];
-    m[k] = x;
+  if (t < K) {
+    double x = red[t * kWaves];
+    for (int w = 1; w < kWaves; ++w) x += red[t * kWaves + w];
+    red[K * kWaves + t] = x;
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) m[k] = red[K * kWaves + k];
   __syncthreads();
 }
 
@@ -68,7 +74,7 @@ __device__ __forceinline__ double node(int i, double dv) { return double(i - N /
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_moments(MomArgs a) {
   constexpr int N3 = N * N * N;
-  __shared__ double red[5 * kWaves];
+  __shared__ double red[5 * (kWaves + 1)];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -78,6 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(MomArgs a) {
     return a.f_fp32 ? double(static_cast<const float*>(a.f)[base + j]) : static_cast<const double*>(a.f)[base + j];
   };
   double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
     const double fj = fval(j);
@@ -97,6 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(MomArgs a) {
     const double cm = rho / ((2.0 * M_PI * T) * sqrt(2.0 * M_PI * T));
     const double ia = 1.0 / (2.0 * T);
     double s[1] = {0.0};
+    #pragma unroll 4
     for (int j = t; j < N3; j += kThreads) {
       const double d1 = node<N>(j / (N * N), a.dv) - u1, d2 = node<N>((j / N) % N, a.dv) - u2,
                    d3 = node<N>(j % N, a.dv) - u3;
@@ -131,7 +139,7 @@ struct ParArgs {
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_imex_params(ParArgs a) {
   constexpr int N3 = N * N * N;
-  __shared__ double red[10 * kWaves];
+  __shared__ double red[10 * (kWaves + 1)];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -139,6 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_imex_params(ParArgs a) {
   const double* f = a.f + size_t(row) * N3;
   const double* tr = a.tr + size_t(row) * N3;
   double m[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
     const double e = v1 * v1 + v2 * v2 + v3 * v3;
@@ -212,7 +221,7 @@ template <int N, int MODE>
 __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   constexpr bool IMEX = MODE == ES_IMEX;
   constexpr int N3 = N * N * N;
-  __shared__ double red[10 * kWaves];
+  __shared__ double red[10 * (kWaves + 1)];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -225,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   };
   // sums of h, v h, v_a v_b h (11, 22, 33, 12, 13, 23)
   double m[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
     const double hj = h(j);
@@ -272,6 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_esbgk(EsArgs a) {
   const double cg = rho / sqrt(8.0 * M_PI * M_PI * M_PI * det);
   const size_t orow = size_t(a.scatter ? row : long(c)) * N3;
   double* out = a.out + orow;
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double d1 = node<N>(j / (N * N), a.dv) - u[0], d2 = node<N>((j / N) % N, a.dv) - u[1],
                  d3 = node<N>(j % N, a.dv) - u[2];
@@ -313,7 +324,7 @@ struct PrArgs {
 template <int N, int MODE>  // MODE 1: stage 2 (forms R2 and A first, then solves in place); 2: solve y into out
 __global__ __launch_bounds__(kThreads) void k_penalty(PrArgs a) {
   constexpr int N3 = N * N * N;
-  __shared__ double red[5 * kWaves];
+  __shared__ double red[5 * (kWaves + 1)];
   const int c = blockIdx.x;
   if (c >= live_cells(a.ncells, a.ncells_dev)) return;
   const int t = threadIdx.x;
@@ -323,6 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_penalty(PrArgs a) {
   double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   [[maybe_unused]] double p1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // Maxwellian of Y1: cm, u, 1/2T, beta
   if constexpr (MODE == 1) {
+    #pragma unroll 4
     for (int j = t; j < N3; j += kThreads) {
       const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
       const double y1 = a.y1[base + j];
@@ -344,6 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_penalty(PrArgs a) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) m[k] = 0.0;
   }
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double v1 = node<N>(j / (N * N), a.dv), v2 = node<N>((j / N) % N, a.dv), v3 = node<N>(j % N, a.dv);
     double r;
@@ -375,6 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_penalty(PrArgs a) {
   const double ia = 1.0 / (2.0 * T);
   const double hb = a.h * 2.0 * M_PI * rho;
   const double den = 1.0 / (eps + hb);
+  #pragma unroll 4
   for (int j = t; j < N3; j += kThreads) {
     const double d1 = node<N>(j / (N * N), a.dv) - u1, d2 = node<N>((j / N) % N, a.dv) - u2,
                  d3 = node<N>(j % N, a.dv) - u3;
