@@ -111,7 +111,8 @@ def serving_run(seconds: float, seed: int = 5):
     """Serving workload: 4 client threads, each keeping two requests in flight;
     a request has N drawn from {16, 24, 32, 48}, M = 32, cells ~ Poisson(512)
     clipped to [16, 4096], FP32 input, FP32 evaluation + FP64 projection;
-    16 GiB arena so that admission by memory binds.  Latency = done - submit."""
+    24 GiB arena (a 4096-cell request at N = 48 needs 20 GB), so that admission
+    by memory binds.  Latency = done - submit."""
     import threading
 
     import numpy as np
@@ -125,7 +126,7 @@ def serving_run(seconds: float, seed: int = 5):
     for n in sizes:
         base = torch.from_numpy(gen.bimaxwellian_batch(32, n, L, seed=seed + n)).float().cuda()
         pool[n] = base.repeat(4096 // 32, 1, 1, 1).contiguous()
-    srv = bz.Server(arena_bytes=16 << 30, max_inflight=16, n_streams=4, max_queue=1 << 16)
+    srv = bz.Server(arena_bytes=24 << 30, max_inflight=16, n_streams=4, max_queue=1 << 16)
     plans = {n: bz.make_plan_desc(n=n, L=L, m=M, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP32)
              for n in sizes}
 
@@ -188,7 +189,7 @@ def serving_run(seconds: float, seed: int = 5):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "cells_per_s": cells[0] / dt, "seconds": dt, "arena_peak_gib": st.arena_peak / 2 ** 30,
             "workload": "4 clients x 2 in flight, N in {16,24,32,48}, M=32, Poisson(512) cells in [16,4096], "
-                        "FP32 + FP64 projection, 16 GiB arena"}
+                        "FP32 + FP64 projection, 24 GiB arena"}
 
 
 def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.0, 0.5, 1.0)):

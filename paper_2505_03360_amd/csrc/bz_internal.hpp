@@ -22,6 +22,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Every workspace starts with a status region: int32 word 0 is set by the
 // output epilogues when they write a non-finite value.
 constexpr size_t kStatusBytes = 256;
+// Directions per launch pair of the chunked plain FP32 path (stage-A volumes
+// kept per cell in the workspace).
+constexpr int kPlainChunk = 4;
 
 // Workspace regions of a bound plan, each [capacity][...].
 struct WsLayout {

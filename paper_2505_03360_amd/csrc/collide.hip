@@ -167,6 +167,23 @@ __device__ __forceinline__ gptr<T> opaque_global(const T* p) {
   return (gptr<T>)p;
 }
 
+// Streaming (non-temporal) access to a complex value: for data touched once
+// per launch, so that it does not evict what the launch re-reads from L2.
+template <typename T>
+__device__ __forceinline__ void nt_store(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> nt_load(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return cx<T>{w.x, w.y};
+}
+
 // ------------------------------------------------------------------ plain passes
 // pass A: X = (alpha + i alpha') fhat, inverse along k3; thread (cell, k2, k1)
 template <typename T, int N>
@@ -311,8 +328,10 @@ __global__ __launch_bounds__(256) void k_rsC(PlainArgs<T> a) {
 //          k1, products accumulated in registers over the chunk, accumulator
 //          kept plane-major acc[cell][j3][j1][j2].
 // Per cell and direction this moves fhat/K + y twice + acc twice/K (K the
-// chunk) instead of fhat + y four times + acc twice.
-constexpr int kPlainChunk = 2;
+// chunk, kPlainChunk) instead of fhat + y four times + acc twice.  k_pA
+// streams fhat in and y out past the L2 (non-temporal), which keeps the
+// chunk's multiplier tables, shared by every cell, resident there.
+using bz::kPlainChunk;
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
@@ -325,7 +344,7 @@ __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
   const cx<T>* fh = a.fh + c * a.fh_stride + off;
   cx<T> F[N];
 #pragma unroll
-  for (int k3 = 0; k3 < N; ++k3) F[k3] = fh[size_t(k3) * N];
+  for (int k3 = 0; k3 < N; ++k3) F[k3] = nt_load(fh + size_t(k3) * N);
   for (int d = 0; d < kPlainChunk; ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
@@ -339,7 +358,7 @@ __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
     bzk::fft<N, 1>(x);
     cx<T>* y = a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(k2) * N + k1;
 #pragma unroll
-    for (int j3 = 0; j3 < N; ++j3) y[size_t(j3) * N * N] = x[j3];
+    for (int j3 = 0; j3 < N; ++j3) nt_store(y + size_t(j3) * N * N, x[j3]);
   }
 }
 
