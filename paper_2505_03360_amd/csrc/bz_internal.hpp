@@ -22,9 +22,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Every workspace starts with a status region: int32 word 0 is set by the
 // output epilogues when they write a non-finite value.
 constexpr size_t kStatusBytes = 256;
-// Directions per launch pair of the chunked plain FP32 path (stage-A volumes
-// kept per cell in the workspace).
-constexpr int kPlainChunk = 4;
+// Directions per launch pair of the chunked plain FP32 path: each keeps one
+// stage-A volume per cell in the workspace, so n = 48 (0.9 MB per volume)
+// takes fewer than the smaller grids.
+constexpr int plain_chunk(int n) { return n <= 32 ? 8 : 4; }
 
 // Workspace regions of a bound plan, each [capacity][...].
 struct WsLayout {

@@ -328,10 +328,10 @@ __global__ __launch_bounds__(256) void k_rsC(PlainArgs<T> a) {
 //          k1, products accumulated in registers over the chunk, accumulator
 //          kept plane-major acc[cell][j3][j1][j2].
 // Per cell and direction this moves fhat/K + y twice + acc twice/K (K the
-// chunk, kPlainChunk) instead of fhat + y four times + acc twice.  k_pA
+// chunk, plain_chunk(N)) instead of fhat + y four times + acc twice.  k_pA
 // streams fhat in and y out past the L2 (non-temporal), which keeps the
 // chunk's multiplier tables, shared by every cell, resident there.
-using bz::kPlainChunk;
+using bz::plain_chunk;
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
   cx<T> F[N];
 #pragma unroll
   for (int k3 = 0; k3 < N; ++k3) F[k3] = nt_load(fh + size_t(k3) * N);
-  for (int d = 0; d < kPlainChunk; ++d) {
+  for (int d = 0; d < plain_chunk(N); ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const cx<T>* mu = a.mult + size_t(p) * N * N * N + off;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
   for (int j1 = 0; j1 < N; ++j1) accr[j1] = (act && !a.first) ? acc[size_t(j1) * N + k] : T(0);
   const long row = a.idx ? long(a.idx[c]) : long(c);
 #pragma unroll 1
-  for (int d = 0; d < kPlainChunk; ++d) {
+  for (int d = 0; d < plain_chunk(N); ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const T wp = a.w[p];
@@ -1133,7 +1133,7 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
     constexpr int NG = N / (4 * plain_planes_per_wave<N>());
     const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
-    for (int p0 = 0; p0 < m1; p0 += kPlainChunk) {
+    for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
       a.pass = p0;
       a.first = p0 == 0;
       hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
