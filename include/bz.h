@@ -467,7 +467,10 @@ bz_status bz_server_destroy(bz_server* server);
  * copied over regime_in so that the next replay continues from the new
  * regimes.  The caller refreshes the contents of the buffers between replays;
  * the pointers are fixed at creation.  The plan must be bound with capacity
- * >= nx*ny and project = 1.  Replays on one plan must be ordered on one stream.
+ * >= nx*ny and project = 1.  The graph holds the plan's tables and workspace
+ * as bound at creation: the plan must not be rebound or destroyed while the
+ * step exists, and replays must be ordered on one stream with every other use
+ * of the plan (they share its workspace).
  */
 typedef struct bz_step bz_step;
 typedef struct {
