@@ -20,6 +20,9 @@ Workload recipes (all seeded with numpy.random.default_rng):
                             Sec. 5 (Tests 2 and 4).
   * ``serving_requests``    request stream of several simulations with grid
                             sizes N in {16,24,32,48} and Poisson cell counts.
+  * ``bimaxwellian2d_batch`` two-velocity-dimension cells (a Maxwellian plus an
+                            anisotropic Gaussian) for the 2D Maxwell-molecule
+                            operator.
 """
 from __future__ import annotations
 
@@ -135,6 +138,40 @@ def bkw_profile(n: int, L: float, K: float) -> np.ndarray:
     r2 = v[:, None, None] ** 2 + v[None, :, None] ** 2 + v[None, None, :] ** 2
     return (2.0 * math.pi * K) ** -1.5 * np.exp(-r2 / (2.0 * K)) * (
         (5.0 * K - 3.0) / (2.0 * K) + (1.0 - K) * r2 / (2.0 * K * K))
+
+
+def maxwellian2d(n: int, L: float, rho: float, u, T: float) -> np.ndarray:
+    """Two-dimensional Maxwellian rho/(2 pi T) exp(-|v-u|^2/(2T)) on the n^2
+    grid v_j = (j - n/2) * 2L/n.  Returns float64 [n][n], index i2 fastest."""
+    v = velocity_axis(n, L)
+    r2 = (v[:, None] - u[0]) ** 2 + (v[None, :] - u[1]) ** 2
+    return rho / (2.0 * math.pi * T) * np.exp(-r2 / (2.0 * T))
+
+
+def gaussian2d(n: int, L: float, rho: float, u, T1: float, T2: float, angle: float) -> np.ndarray:
+    """Anisotropic 2D Gaussian: temperature T1 along the direction at ``angle``
+    (radians from the v1 axis) and T2 across it."""
+    v = velocity_axis(n, L)
+    V1, V2 = np.meshgrid(v - u[0], v - u[1], indexing="ij")
+    a = V1 * math.cos(angle) + V2 * math.sin(angle)
+    b = -V1 * math.sin(angle) + V2 * math.cos(angle)
+    return rho / (2.0 * math.pi * math.sqrt(T1 * T2)) * np.exp(-a * a / (2.0 * T1) - b * b / (2.0 * T2))
+
+
+def bimaxwellian2d_batch(ncells: int, n: int, L: float, seed: int) -> np.ndarray:
+    """Cells rho1 M(u1,T1) + rho2 G(u2,T2a,T2b) in two velocity dimensions:
+    rho_i ~ U[0.5,1.5], u_i ~ U[-1,1]^2, T ~ U[0.5,2], the second component
+    anisotropic (temperature ratio <= 3.5, random orientation)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((ncells, n, n))
+    for c in range(ncells):
+        rho1, rho2 = rng.uniform(0.5, 1.5, size=2)
+        u1, u2 = rng.uniform(-1.0, 1.0, size=(2, 2))
+        T1 = rng.uniform(0.5, 2.0)
+        Ta = rng.uniform(0.5, 2.0)
+        Tb = Ta * rng.uniform(1.0, 3.5)
+        out[c] = maxwellian2d(n, L, rho1, u1, T1) + gaussian2d(n, L, rho2, u2, Ta, Tb, rng.uniform(0.0, math.pi))
+    return out
 
 
 def bow_shock_field(nx: int, ny: int, step: int, seed: int, noise: float = 0.01):

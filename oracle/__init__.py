@@ -12,6 +12,10 @@ Modules
               (Carleman, direction-quadrature) form, written with naive
               separable DFTs and a direct loop over directions; the
               conservative moment projection.
+  maxwell2d   the same fast spectral operator for Maxwell molecules in two
+              velocity dimensions (the 2d case of Sec. 4.4.1: constant
+              Carleman kernel, equally spaced angles on the half circle) and
+              its projection on the four invariants of two dimensions.
   directions  hemisphere quadrature rules (icosahedral axes, the paper's
               (theta, phi) product grid, equal-weight golden spiral).
   kinetic     macroscopic fields, the Maxwellian, the L1 distance of the
