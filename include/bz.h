@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define BZ_ABI_VERSION 2
+#define BZ_ABI_VERSION 3
 
 typedef int32_t bz_status;
 
@@ -55,7 +55,9 @@ enum {
   BZ_DIRS_EXPLICIT = 0, /* use desc.dirs / desc.weights */
   BZ_DIRS_ICOSA6 = 1,   /* six icosahedral axes, weight pi/3 (m must be 6) */
   BZ_DIRS_PRODUCT = 2,  /* theta_p=(p+1/2)pi/a1, phi_q=q pi/a2, weights ~ sin(theta) */
-  BZ_DIRS_SPIRAL = 3    /* equal-weight golden spiral, z_p=(p+1/2)/m */
+  BZ_DIRS_SPIRAL = 3,   /* equal-weight golden spiral, z_p=(p+1/2)/m */
+  BZ_DIRS_CIRCLE = 4    /* two velocity dimensions: theta_p = pi p/m, p = 1..m,
+                           weight pi/m each (the only rule of dim = 2 plans) */
 };
 
 /* evaluation strategy */
@@ -101,6 +103,13 @@ typedef struct {
                             1: truncated convolution without wrap-around
                             (l + m = k over the series' own modes), evaluated
                             by the 3/2 rule on a padded 3n/2 grid; n = 16, 32 */
+  int32_t dim;           /* velocity dimensions: 0 or 3 (the operator above), or 2:
+                            Maxwell molecules in two velocity dimensions (Sec.
+                            4.4.1, the 2d case): f is [n][n], gamma must be 0,
+                            Btilde = kernel_c (the paper's normalisation is 1),
+                            dir_kind BZ_DIRS_CIRCLE, n in {16, 32, 64} (FP64:
+                            16, 32), one fused kernel (transform AUTO or FUSED),
+                            dealias, chunks and slices 0 */
 } bz_plan_desc;
 
 typedef struct bz_plan bz_plan;
@@ -122,6 +131,11 @@ const char* bz_last_error(void);
  *   alpha'_p(k) = psi_R(|kappa_k - (kappa_k . e_p) e_p|), psi_R(r) = 2 pi R J1(R r)/r,
  * the loss multiplier Bhat_M(k) = sum_p w_p alpha_p(k) alpha'_p(k), and the
  * inverse Gram matrix of the five collision invariants (hypothesis (H1)).
+ * dim = 2 (Sec. 4.4.1, the 2d case): alpha_p(k) = phi(kappa_k . e_p),
+ * alpha'_p(k) = phi(kappa_k . e_p'), phi(s) = 2R sinc(R s), e_p = (cos, sin)
+ * theta_p, e_p' = e_p turned by pi/2, w_p = pi/m, and the four invariants
+ * (1, v1, v2, |v|^2); bz_collide_batch then takes distributions of n^2 values
+ * [i1][i2] (batches [cells][n][n]) and returns Q in the same layout.
  * *out receives a heap object owned by the caller (bz_plan_destroy).
  */
 bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out);
@@ -160,11 +174,13 @@ bz_status bz_set_tune_table(const char* path);
 /* Strategy the plan resolved to: transform, chunks, slices. */
 bz_status bz_plan_strategy(const bz_plan* plan, int32_t* transform, int32_t* chunks, int32_t* slices);
 
-/* Host copies of the plan's direction rule: dirs [m][3], weights [m]. */
+/* Host copies of the plan's direction rule: dirs [m][3], weights [m]
+   (dim = 2: (cos theta_p, sin theta_p, 0) and pi/m). */
 bz_status bz_plan_get_rule(const bz_plan* plan, double* dirs, double* weights);
 
 /* Host copy of the FP64 multipliers of pass p (0 <= p <= m; pass m is the
-   loss pass (Bhat_M, 1)) as [k2][k3][k1][2] = (alpha_p, alpha'_p). */
+   loss pass (Bhat_M, 1)) as [k2][k3][k1][2] = (alpha_p, alpha'_p)
+   (dim = 2: [k2][k1][2]). */
 bz_status bz_plan_get_multipliers(const bz_plan* plan, int32_t p, double* out);
 
 /*

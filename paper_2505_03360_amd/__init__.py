@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbz.so")
 BZ_OK, BZ_AGAIN = 0, 1
 BZ_ERR_ARG, BZ_ERR_UNSUPPORTED, BZ_ERR_DEVICE, BZ_ERR_NOMEM, BZ_ERR_STATE, BZ_ERR_NUMERIC = -1, -2, -3, -4, -5, -6
 BZ_FP64, BZ_FP32 = 0, 1
-BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL = 0, 1, 2, 3
+BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL, BZ_DIRS_CIRCLE = 0, 1, 2, 3, 4
 BZ_XF_AUTO, BZ_XF_FUSED, BZ_XF_PLAIN = 0, 1, 2
 BZ_SCATTER = 1
 BZ_CELL_SOLID, BZ_CELL_FORCE_BOLTZMANN = 1, 2
@@ -48,6 +48,7 @@ class BzPlanDesc(ctypes.Structure):
         ("chunks", ctypes.c_int32),
         ("slices", ctypes.c_int32),
         ("dealias", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
     ]
 
 
@@ -115,7 +116,7 @@ class BzError(RuntimeError):
 
 
 _LIB = None
-ABI_VERSION = 2  # the struct layouts below match include/bz.h at this version
+ABI_VERSION = 3  # the struct layouts below match include/bz.h at this version
 
 # (name, restype, argtypes) for every symbol declared in include/bz.h
 _VP = ctypes.c_void_p
@@ -199,16 +200,26 @@ def bz_last_error() -> str:
     return lib().bz_last_error().decode()
 
 
+def make_plan2d_desc(n: int, L: float = 8.0, R: float = 0.0, kernel_c: float = 1.0, m: int = 32,
+                     precision: int = BZ_FP32, project: int = 1, max_cells: int = 1) -> BzPlanDesc:
+    """Descriptor of the two-velocity-dimension Maxwell-molecule operator
+    (gamma = 0, angles theta_p = pi p/m); kernel_c = 1 is the paper's Btilde = 1."""
+    return make_plan_desc(n=n, L=L, R=R, gamma=0.0, kernel_c=kernel_c, m=m, dir_kind=BZ_DIRS_CIRCLE,
+                          precision=precision, project=project, max_cells=max_cells, dim=2)
+
+
 def make_plan_desc(n: int, L: float = 8.0, R: float = 0.0, gamma: float = 1.0, kernel_c: float = 4.0,
                    m: int = 6, dir_kind: int = BZ_DIRS_ICOSA6, dirs=None, weights=None, a1: int = 0,
                    a2: int = 0, precision: int = BZ_FP32, transform: int = BZ_XF_AUTO, project: int = 1,
-                   max_cells: int = 1, chunks: int = 0, slices: int = 0, dealias: int = 0) -> BzPlanDesc:
+                   max_cells: int = 1, chunks: int = 0, slices: int = 0, dealias: int = 0,
+                   dim: int = 3) -> BzPlanDesc:
     d = BzPlanDesc()
     d.n, d.L, d.R, d.gamma, d.kernel_c = n, L, R, gamma, kernel_c
     d.m, d.dir_kind, d.a1, d.a2 = m, dir_kind, a1, a2
     d.precision, d.transform, d.project, d.max_cells, d.chunks = precision, transform, project, max_cells, chunks
     d.slices = slices
     d.dealias = dealias
+    d.dim = dim
     d._keep = []
     if dirs is not None:
         import numpy as np
@@ -272,11 +283,15 @@ def bz_plan_get_rule(plan: int, m: int):
     return d, w
 
 
-def bz_plan_get_multipliers(plan: int, n: int, p: int):
-    """FP64 host multipliers of pass p as ([k1][k2][k3] alpha, alpha')."""
+def bz_plan_get_multipliers(plan: int, n: int, p: int, dim: int = 3):
+    """FP64 host multipliers of pass p as ([k1][k2][k3] alpha, alpha'), or
+    ([k1][k2] alpha, alpha') for a two-dimensional plan."""
     import numpy as np
-    buf = np.zeros(n ** 3 * 2)
+    buf = np.zeros(n ** dim * 2)
     _check(lib().bz_plan_get_multipliers(plan, p, buf.ctypes.data_as(_c_double_p)))
+    if dim == 2:
+        t = buf.reshape(n, n, 2)  # [k2][k1]
+        return t[..., 0].T.copy(), t[..., 1].T.copy()
     t = buf.reshape(n, n, n, 2)  # [k2][k3][k1]
     return t[..., 0].transpose(2, 0, 1).copy(), t[..., 1].transpose(2, 0, 1).copy()
 
@@ -427,6 +442,7 @@ class Collider:
         torch = _torch()
         self.desc = make_plan_desc(n=n, max_cells=max_cells, **desc_kw)
         self.n = n
+        self.dim = 2 if self.desc.dim == 2 else 3
         self.plan = bz_plan_create(self.desc)
         tb, fixed, per = bz_plan_device_bytes(self.plan)
         self.tables = torch.empty(max(tb, 256), dtype=torch.uint8, device=device)
@@ -439,7 +455,7 @@ class Collider:
 
     def __call__(self, f, idx=None, ncells=None, ncells_dev=None, out=None, scatter=False, stream=None):
         torch = _torch()
-        n3 = self.n ** 3
+        n3 = self.n ** self.dim
         if f.dtype not in (torch.float32, torch.float64) or not f.is_contiguous() or not f.is_cuda:
             raise ValueError("f must be a contiguous CUDA float32/float64 tensor")
         if ncells is None:
@@ -447,7 +463,7 @@ class Collider:
         if idx is not None and (idx.dtype != torch.int32 or not idx.is_cuda):
             raise ValueError("idx must be a CUDA int32 tensor")
         if out is None:
-            out = torch.empty((ncells, self.n, self.n, self.n), dtype=self.out_dtype, device=f.device)
+            out = torch.empty((ncells,) + (self.n,) * self.dim, dtype=self.out_dtype, device=f.device)
         fd = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
         bz_collide_batch(self.plan, _ptr(f), fd, _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
                          BZ_SCATTER if scatter else 0, _stream(stream))
@@ -589,7 +605,7 @@ class Server:
 
     def submit(self, f, q, plan: BzPlanDesc, idx=None, ncells=None, scatter=False, client_id=0):
         torch = _torch()
-        n3 = plan.n ** 3
+        n3 = plan.n ** (2 if plan.dim == 2 else 3)
         r = BzRequest()
         r.plan = plan
         r.f = _ptr(f)

@@ -51,6 +51,8 @@ struct Binding {
 struct bz_plan {
   bz_plan_desc d{};  // copy of the descriptor (dirs/weights pointers cleared)
   int n = 0;         // points per axis
+  int dim = 3;       // velocity dimensions (2: Maxwell molecules in two dimensions)
+  size_t npts = 0;   // n^dim grid points per cell
   int m = 0;         // directions
   int m1 = 0;        // m + 1: the loss term is evaluated as one more pass
   double L = 0, R = 0, gamma = 1, C = 4, dv = 0;
@@ -67,7 +69,7 @@ struct bz_plan {
   std::vector<double> mult;
   std::vector<double> wext;     // [m1] device weights: w_p, then the loss scale
   std::vector<double> pscale;   // [m1] per-pass balance factor of the packed transform
-  double ginv[25] = {};         // (C C^T)^-1 of the five invariants
+  double ginv[25] = {};         // (C C^T)^-1 of the five invariants (dim = 2: 4x4 of four)
   size_t table_mult_bytes = 0, table_w_off = 0, tables_bytes = 0;
   size_t ws_fixed = 0, ws_per_cell = 0;
   // binding
@@ -90,6 +92,9 @@ namespace bz {
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
                          int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex = nullptr);
+// two velocity dimensions (collide2d.hip)
+bz_status launch_collide2d(const bz_plan* p, const Binding& b, const void* f, int f_fp32, const int32_t* idx,
+                           int ncells, const int32_t* ncells_dev, void* q, int scatter, hipStream_t s, bool timed);
 // clears a status word with a vector store (collide.hip)
 void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s);
 // per-cell IMEX parameters (kinetic.hip)

@@ -1305,6 +1305,10 @@ int fused_default_chunks(int n) { return 1; }
 bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int f_fp32,
                          const int32_t* idx, int ncells, const int32_t* ncells_dev, void* q,
                          int scatter, hipStream_t s, bool timed, const bzk::ImexDev* imex) {
+  if (p->dim == 2) {
+    if (imex) return fail(BZ_ERR_UNSUPPORTED, "IMEX update: three velocity dimensions only");
+    return launch_collide2d(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed);
+  }
   if (p->pad) {
     if (p->fp32)
       return p->n == 16 ? launch_dealiased<float, 16, 24>(p, b, f, f_fp32, idx, ncells, ncells_dev, q, scatter, s, timed, imex)

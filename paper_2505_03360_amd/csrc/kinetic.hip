@@ -585,6 +585,7 @@ constexpr double kPrGamma = 0.29289321881345248;  // 1 - 1/sqrt(2), the implicit
 
 bz_status pr_check(const char* who, const bz_plan* p, const bz_imex_desc* d, int32_t ncells) {
   if (!p) return bz::fail(BZ_ERR_ARG, "%s: null plan", who);
+  if (p->dim == 2) return bz::fail(BZ_ERR_UNSUPPORTED, "%s: three velocity dimensions only", who);
   if (!d) return bz::fail(BZ_ERR_ARG, "%s: null descriptor", who);
   if (!p->ws_dev) return bz::fail(BZ_ERR_STATE, "%s: plan not bound", who);
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return bz::fail(BZ_ERR_ARG, "%s: dt must be > 0", who);

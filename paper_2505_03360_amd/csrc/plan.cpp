@@ -141,34 +141,36 @@ double psi_R(double r, double R) {
   return 2.0 * kPi * R * ::j1(R * r) / r;
 }
 
-// 5x5 symmetric positive definite inverse by Cholesky.
-bool spd_inverse5(const double G[25], double out[25]) {
-  double Lc[25] = {};
-  for (int i = 0; i < 5; ++i)
+// Inverse of a symmetric positive definite K x K matrix (row-major) by
+// Cholesky factorisation; false if G is not positive definite.
+template <int K>
+bool spd_inverse(const double* G, double* out) {
+  double Lc[K * K] = {};
+  for (int i = 0; i < K; ++i)
     for (int j = 0; j <= i; ++j) {
-      double s = G[5 * i + j];
-      for (int k = 0; k < j; ++k) s -= Lc[5 * i + k] * Lc[5 * j + k];
+      double s = G[K * i + j];
+      for (int k = 0; k < j; ++k) s -= Lc[K * i + k] * Lc[K * j + k];
       if (i == j) {
         if (!(s > 0.0)) return false;
-        Lc[5 * i + i] = std::sqrt(s);
+        Lc[K * i + i] = std::sqrt(s);
       } else {
-        Lc[5 * i + j] = s / Lc[5 * j + j];
+        Lc[K * i + j] = s / Lc[K * j + j];
       }
     }
   // columns of the inverse: solve L L^T x = e_c
-  for (int c = 0; c < 5; ++c) {
-    double y[5], x[5];
-    for (int i = 0; i < 5; ++i) {
+  for (int c = 0; c < K; ++c) {
+    double y[K], x[K];
+    for (int i = 0; i < K; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) s -= Lc[5 * i + k] * y[k];
-      y[i] = s / Lc[5 * i + i];
+      for (int k = 0; k < i; ++k) s -= Lc[K * i + k] * y[k];
+      y[i] = s / Lc[K * i + i];
     }
-    for (int i = 4; i >= 0; --i) {
+    for (int i = K - 1; i >= 0; --i) {
       double s = y[i];
-      for (int k = i + 1; k < 5; ++k) s -= Lc[5 * k + i] * x[k];
-      x[i] = s / Lc[5 * i + i];
+      for (int k = i + 1; k < K; ++k) s -= Lc[K * k + i] * x[k];
+      x[i] = s / Lc[K * i + i];
     }
-    for (int i = 0; i < 5; ++i) out[5 * i + c] = x[i];
+    for (int i = 0; i < K; ++i) out[K * i + c] = x[i];
   }
   return true;
 }
@@ -236,9 +238,14 @@ void build_tables(bz_plan* p) {
 // (Bhat_M/sL, sL [k on a Nyquist plane]).
 void device_multiplier(const bz_plan* p, int pass, size_t i, double& re, double& im) {
   const int n = p->n;
-  const size_t n3 = size_t(n) * n * n;
-  const int k1 = int(i % n), k3 = int((i / n) % n), k2 = int(i / (size_t(n) * n));
-  const bool nyq = k1 == n / 2 || k2 == n / 2 || k3 == n / 2;
+  const size_t n3 = p->npts;
+  bool nyq;
+  if (p->dim == 2) {  // [k2][k1]
+    nyq = int(i % n) == n / 2 || int(i / n) == n / 2;
+  } else {            // [k2][k3][k1]
+    const int k1 = int(i % n), k3 = int((i / n) % n), k2 = int(i / (size_t(n) * n));
+    nyq = k1 == n / 2 || k2 == n / 2 || k3 == n / 2;
+  }
   const double* a = &p->mult[size_t(pass) * n3 * 2];
   const double s = p->pscale[pass];
   if (pass < p->m) {
@@ -261,7 +268,131 @@ bool build_gram_inverse(bz_plan* p) {
         for (int a = 0; a < 5; ++a)
           for (int b = 0; b < 5; ++b) G[5 * a + b] += c[a] * c[b];
       }
-  return spd_inverse5(G, p->ginv);
+  return spd_inverse<5>(G, p->ginv);
+}
+
+// ---------------------------------------------------------------- two velocity dimensions
+// Maxwell molecules in two velocity dimensions (Sec. 4.4.1, the 2d case):
+// Btilde = C, angles theta_p = pi p / m (p = 1..m) of weight pi/m, and
+//   alpha_p(k) = phi(kappa_k . e_p), alpha'_p(k) = phi(kappa_k . e_p'),
+//   phi(s) = 2 R sinc(R s), e_p = (cos theta_p, sin theta_p), e_p' = e_p turned by pi/2.
+// Host tables [p][k2][k1] x (a, a'), the loss pass (Bhat_M, 1) last.
+void build_tables2d(bz_plan* p) {
+  const int n = p->n;
+  const size_t n2 = size_t(n) * n;
+  std::vector<double> kap(n);
+  for (int k = 0; k < n; ++k) kap[k] = (kPi / p->L) * double(k < n / 2 ? k : k - n);
+  p->w.assign(p->m, kPi / p->m);
+  p->dirs.assign(size_t(3) * p->m, 0.0);  // (cos, sin, 0) theta_p
+  for (int dir = 0; dir < p->m; ++dir) {
+    p->dirs[3 * dir] = std::cos(kPi * double(dir + 1) / p->m);
+    p->dirs[3 * dir + 1] = std::sin(kPi * double(dir + 1) / p->m);
+  }
+  p->mult.assign(size_t(p->m1) * n2 * 2, 0.0);
+  auto phi = [&](double x) { const double y = p->R * x; return 2.0 * p->R * (y == 0.0 ? 1.0 : std::sin(y) / y); };
+  for (int dir = 0; dir < p->m; ++dir) {
+    const double th = kPi * double(dir + 1) / p->m;
+    const double c = std::cos(th), sn = std::sin(th);
+    double* out = &p->mult[size_t(dir) * n2 * 2];
+    for (int k2 = 0; k2 < n; ++k2)
+      for (int k1 = 0; k1 < n; ++k1) {
+        const size_t o = 2 * (size_t(k2) * n + k1);
+        out[o] = phi(kap[k1] * c + kap[k2] * sn);
+        out[o + 1] = phi(-kap[k1] * sn + kap[k2] * c);
+      }
+  }
+  double* loss = &p->mult[size_t(p->m) * n2 * 2];
+  for (int dir = 0; dir < p->m; ++dir) {
+    const double* a = &p->mult[size_t(dir) * n2 * 2];
+    for (size_t i = 0; i < n2; ++i) loss[2 * i] += p->w[dir] * a[2 * i] * a[2 * i + 1];
+  }
+  for (size_t i = 0; i < n2; ++i) loss[2 * i + 1] = 1.0;
+  // balance factors as in three dimensions (alpha and alpha' share phi: s = 1)
+  p->pscale.assign(p->m1, 1.0);
+  for (int dir = 0; dir < p->m; ++dir) {
+    const double* a = &p->mult[size_t(dir) * n2 * 2];
+    double ma = 0.0, mb = 0.0;
+    for (size_t i = 0; i < n2; ++i) {
+      ma = std::max(ma, std::fabs(a[2 * i]));
+      mb = std::max(mb, std::fabs(a[2 * i + 1]));
+    }
+    p->pscale[dir] = (ma > 0.0 && mb > 0.0) ? std::sqrt(mb / ma) : 1.0;
+  }
+  p->pscale[p->m] = std::sqrt(std::fabs(loss[0]) > 0.0 ? std::fabs(loss[0]) : 1.0);
+  p->wext.assign(p->w.begin(), p->w.end());
+  p->wext.push_back(p->pscale[p->m]);
+}
+
+// (C C^T)^-1 of the invariants (1, v1, v2, |v|^2) of two velocity dimensions.
+bool build_gram_inverse2d(bz_plan* p) {
+  const int n = p->n;
+  double G[16] = {};
+  for (int i1 = 0; i1 < n; ++i1)
+    for (int i2 = 0; i2 < n; ++i2) {
+      const double v1 = (i1 - n / 2) * p->dv, v2 = (i2 - n / 2) * p->dv;
+      const double c[4] = {1.0, v1, v2, v1 * v1 + v2 * v2};
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) G[4 * a + b] += c[a] * c[b];
+    }
+  return spd_inverse<4>(G, p->ginv);
+}
+
+// One fused kernel keeps every intermediate of a cell on chip: the workspace
+// holds only the status word (and a token 256 bytes per cell, so that the
+// capacity of a binding still counts cells).
+void layout2d(bz_plan* p) {
+  const size_t es = p->fp32 ? 4 : 8;
+  p->table_mult_bytes = align256(size_t(p->m1) * p->npts * 2 * es);
+  p->table_w_off = p->table_mult_bytes;
+  p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
+  p->ws = WsLayout{};
+  p->ws.fh_cell = 256;
+  p->ws_fixed = kStatusBytes;
+  p->ws_per_cell = p->ws.fh_cell;
+}
+
+bz_status create_plan2d(const bz_plan_desc& d, bz_plan** out) {
+  if (!(d.n == 16 || d.n == 32 || d.n == 64))
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: two-dimensional plans need n in {16,32,64}, got %d", d.n);
+  if (d.precision == BZ_FP64 && d.n == 64)
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: two-dimensional FP64 plans need n in {16,32}");
+  if (d.gamma != 0.0)
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: two velocity dimensions are Maxwell molecules (gamma = 0)");
+  if (d.dir_kind != BZ_DIRS_CIRCLE)
+    return fail(BZ_ERR_ARG, "bz_plan_create: two-dimensional plans take dir_kind BZ_DIRS_CIRCLE");
+  if (d.transform == BZ_XF_PLAIN)
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: two-dimensional plans have one (fused) kernel");
+  if (d.dealias || d.chunks || d.slices)
+    return fail(BZ_ERR_ARG, "bz_plan_create: two-dimensional plans take dealias, chunks and slices 0");
+  const double R = d.R > 0.0 ? d.R : (std::sqrt(2.0) - 1.0) * d.L;
+  bz_plan* p = new bz_plan();
+  p->d = d;
+  p->d.dirs = nullptr;
+  p->d.weights = nullptr;
+  p->d.R = R;
+  p->dim = 2;
+  p->n = d.n;
+  p->npts = size_t(d.n) * d.n;
+  p->m = d.m;
+  p->m1 = d.m + 1;
+  p->L = d.L;
+  p->R = R;
+  p->gamma = 0.0;
+  p->C = d.kernel_c;
+  p->dv = 2.0 * d.L / d.n;
+  p->fp32 = d.precision == BZ_FP32;
+  p->project = d.project ? 1 : 0;
+  p->transform = BZ_XF_FUSED;
+  p->chunks = 1;
+  p->slices = 1;
+  build_tables2d(p);
+  if (!build_gram_inverse2d(p)) {
+    delete p;
+    return fail(BZ_ERR_NUMERIC, "bz_plan_create: Gram matrix not positive definite");
+  }
+  layout2d(p);
+  *out = p;
+  return BZ_OK;
 }
 
 // ---------------------------------------------------------------- tune table
@@ -374,7 +505,7 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
 
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
   if (p->pad) return upload_tables(p->pad, tables_dev, s);
-  const size_t n3 = size_t(p->n) * p->n * p->n;
+  const size_t n3 = p->npts;
   std::vector<unsigned char> host(p->tables_bytes, 0);
   const size_t entries = size_t(p->m1) * n3;
   if (p->fp32) {
@@ -415,6 +546,19 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   if (!desc || !out) return fail(BZ_ERR_ARG, "bz_plan_create: null argument");
   *out = nullptr;
   const bz_plan_desc& d = *desc;
+  if (d.dim != 0 && d.dim != 2 && d.dim != 3) return fail(BZ_ERR_ARG, "bz_plan_create: dim must be 0, 2 or 3");
+  if (d.dim == 2) {
+    if (!(d.L > 0.0) || !std::isfinite(d.L)) return fail(BZ_ERR_ARG, "bz_plan_create: L must be > 0");
+    const double rmax2 = 4.0 * d.L / (3.0 + std::sqrt(2.0));
+    if (d.R > 0.0 && !(d.R <= rmax2 * (1.0 + 1e-12)))
+      return fail(BZ_ERR_ARG, "bz_plan_create: R=%.17g exceeds the non-overlap bound 4L/(3+sqrt2)=%.17g", d.R, rmax2);
+    if (!(d.kernel_c > 0.0) || !std::isfinite(d.kernel_c)) return fail(BZ_ERR_ARG, "bz_plan_create: kernel_c must be > 0");
+    if (d.m < 1 || d.m > 512) return fail(BZ_ERR_ARG, "bz_plan_create: m=%d not in 1..512", d.m);
+    if (d.precision != BZ_FP32 && d.precision != BZ_FP64) return fail(BZ_ERR_ARG, "bz_plan_create: bad precision");
+    if (d.transform < BZ_XF_AUTO || d.transform > BZ_XF_PLAIN) return fail(BZ_ERR_ARG, "bz_plan_create: bad transform");
+    if (d.max_cells < 1) return fail(BZ_ERR_ARG, "bz_plan_create: max_cells must be >= 1");
+    return create_plan2d(d, out);
+  }
   if (!(d.n == 16 || d.n == 24 || d.n == 32 || d.n == 48))
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: n=%d not in {16,24,32,48}", d.n);
   if (!(d.L > 0.0) || !std::isfinite(d.L)) return fail(BZ_ERR_ARG, "bz_plan_create: L must be > 0");
@@ -439,6 +583,8 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   p->d.dirs = nullptr;
   p->d.weights = nullptr;
   p->n = d.n;
+  p->npts = size_t(d.n) * d.n * d.n;
+  p->d.dim = 3;
   p->m = d.m;
   p->m1 = d.m + 1;
   p->L = d.L;
@@ -631,7 +777,7 @@ bz_status bz_plan_get_multipliers(const bz_plan* p, int32_t pass, double* out) {
   clear_error();
   if (!p || !out) return fail(BZ_ERR_ARG, "bz_plan_get_multipliers: null argument");
   if (pass < 0 || pass > p->m) return fail(BZ_ERR_ARG, "bz_plan_get_multipliers: pass %d not in 0..m", pass);
-  const size_t n3 = size_t(p->n) * p->n * p->n;
+  const size_t n3 = p->npts;
   std::memcpy(out, &p->mult[size_t(pass) * n3 * 2], sizeof(double) * n3 * 2);
   return BZ_OK;
 }
@@ -703,6 +849,7 @@ bz_status bz_imex_euler(const bz_plan* p, const bz_imex_desc* d, const double* f
                         int32_t flags, void* stream) {
   clear_error();
   if (!p) return fail(BZ_ERR_ARG, "bz_imex_euler: null plan");
+  if (p->dim == 2) return fail(BZ_ERR_UNSUPPORTED, "bz_imex_euler: three velocity dimensions only");
   if (!d) return fail(BZ_ERR_ARG, "bz_imex_euler: null descriptor");
   if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_imex_euler: plan not bound");
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(BZ_ERR_ARG, "bz_imex_euler: dt must be > 0");

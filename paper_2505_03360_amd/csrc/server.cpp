@@ -98,7 +98,7 @@ struct PlanKey {
            d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
            d.a2 == o.d.a2 && d.precision == o.d.precision && d.transform == o.d.transform &&
            d.project == o.d.project && d.chunks == o.d.chunks && d.slices == o.d.slices &&
-           d.dealias == o.d.dealias && dirs == o.dirs &&
+           d.dealias == o.d.dealias && (d.dim == 2) == (o.d.dim == 2) && dirs == o.dirs &&
            weights == o.weights;
   }
 };

@@ -24,6 +24,7 @@ bz_status bz_step_create(const bz_plan* plan, const bz_mask_desc* mask, const bz
   bz::clear_error();
   if (!plan || !mask || !b || !out) return bz::fail(BZ_ERR_ARG, "bz_step_create: null argument");
   *out = nullptr;
+  if (plan->dim == 2) return bz::fail(BZ_ERR_UNSUPPORTED, "bz_step_create: three velocity dimensions only");
   if (!plan->ws_dev) return bz::fail(BZ_ERR_STATE, "bz_step_create: plan not bound");
   const long ncell = long(mask->nx) * mask->ny;
   if (ncell > plan->capacity)

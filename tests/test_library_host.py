@@ -188,3 +188,66 @@ def test_esbgk_pr222_validation():
         with pytest.raises(bz.BzError) as e:
             fn(d, bz.BzImexDesc(-1.0, 0.1, None), *args)
         assert e.value.code == bz.BZ_ERR_ARG  # dt <= 0
+
+
+# ---------------------------------------------------------------- two velocity dimensions
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=24), bz.BZ_ERR_UNSUPPORTED),                      # n not in {16, 32, 64}
+    (dict(n=64, precision=bz.BZ_FP64), bz.BZ_ERR_UNSUPPORTED),
+    (dict(gamma=1.0), bz.BZ_ERR_UNSUPPORTED),                 # Maxwell molecules only
+    (dict(dir_kind=bz.BZ_DIRS_SPIRAL), bz.BZ_ERR_ARG),
+    (dict(transform=bz.BZ_XF_PLAIN), bz.BZ_ERR_UNSUPPORTED),
+    (dict(dealias=1), bz.BZ_ERR_ARG),
+    (dict(chunks=2), bz.BZ_ERR_ARG),
+    (dict(R=10.0), bz.BZ_ERR_ARG),                            # beyond 4L/(3+sqrt2)
+    (dict(m=0), bz.BZ_ERR_ARG),
+    (dict(dim=5), bz.BZ_ERR_ARG),
+])
+def test_plan2d_validation(kw, code):
+    args = dict(n=32, L=8.0, gamma=0.0, kernel_c=1.0, m=16, dir_kind=bz.BZ_DIRS_CIRCLE, dim=2)
+    args.update(kw)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_create(bz.make_plan_desc(**args))
+    assert e.value.code == code
+
+
+def test_circle_rule_refused_in_three_dimensions():
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_plan_create(bz.make_plan_desc(n=16, m=8, dir_kind=bz.BZ_DIRS_CIRCLE))
+    assert e.value.code == bz.BZ_ERR_ARG
+
+
+@pytest.mark.parametrize("n,m,R", [(16, 8, 0.0), (32, 24, 5.5), (64, 5, 0.0)])
+def test_plan2d_tables_match_oracle(n, m, R):
+    from oracle import maxwell2d as m2
+    L = 7.0
+    p = bz.bz_plan_create(bz.make_plan2d_desc(n, L=L, R=R, kernel_c=1.7, m=m))
+    plan = m2.make_plan(n, L, R=R if R > 0 else None, A=m, kernel_c=1.7)
+    for q in (0, m // 2, m - 1):
+        a, b = bz.bz_plan_get_multipliers(p, n, q, dim=2)
+        ra, rb = m2.multipliers(plan, q)
+        assert np.abs(a - ra).max() <= 1e-13 * np.abs(ra).max()
+        assert np.abs(b - rb).max() <= 1e-13 * np.abs(rb).max()
+    bl, one = bz.bz_plan_get_multipliers(p, n, m, dim=2)
+    assert np.abs(bl - m2.bhat_m(plan)).max() <= 1e-13 * np.abs(bl).max()
+    assert np.all(one == 1.0)
+    d, w = bz.bz_plan_get_rule(p, m)
+    th = math.pi * np.arange(1, m + 1) / m
+    assert np.abs(d[:, 0] - np.cos(th)).max() <= 1e-15 and np.abs(d[:, 1] - np.sin(th)).max() <= 1e-15
+    assert np.all(d[:, 2] == 0.0) and abs(w.sum() - math.pi) <= 1e-13
+    assert bz.bz_plan_transform(p) == bz.BZ_XF_FUSED
+    t, fixed, per = bz.bz_plan_device_bytes(p)
+    assert t >= (m + 1) * n * n * 8 and per > 0
+    bz.bz_plan_destroy(p)
+
+
+def test_plan2d_refused_by_three_dimensional_entry_points():
+    p = bz.bz_plan_create(bz.make_plan2d_desc(16, m=4))
+    d = bz.BzImexDesc(0.01, 0.1, None)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_imex_euler(p, d, 1, 1, 0, 1, 0, 1, 0, 0)
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_pr222_stage1(p, d, 1, 0, 1, 0, 2, 0)
+    assert e.value.code == bz.BZ_ERR_UNSUPPORTED
+    bz.bz_plan_destroy(p)
