@@ -335,6 +335,47 @@ def dealias_run(f, q_circ, steps: int):
             "workload": f"{f.shape[0]} cells N=32 (padded 48) M=32 FP32 + FP64 projection"}
 
 
+def maxwell2d_run(steps: int, n: int = 64, m: int = 32, cells: int = 4096):
+    """The two-velocity-dimension Maxwell-molecule operator (dim = 2 plans):
+    `cells` seeded 2D cells (a Maxwellian plus an anisotropic Gaussian), n^2
+    grid, m angles, FP32 + FP64 projection, Btilde = 1.  Algorithmic work per
+    cell in the FFT method's count: a real forward transform, one complex 2D
+    transform per angle and for the loss pass (5 n^2 log2 n^2 each), 6 flops
+    per point per angle for multipliers and products."""
+    import math
+
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    f = torch.from_numpy(gen.bimaxwellian2d_batch(cells, n, L, seed=11)).cuda()
+    col = bz.Collider(n, cells, L=L, gamma=0.0, kernel_c=1.0, m=m, dir_kind=bz.BZ_DIRS_CIRCLE,
+                      precision=bz.BZ_FP32, dim=2)
+    q = col(f)
+    torch.cuda.synchronize()
+    bz.bz_plan_set_timing(col.plan, True)
+    for _ in range(steps):
+        col(f, out=q)
+    kernel_ms = bz.bz_plan_last_times(col.plan)[1]
+    bz.bz_plan_set_timing(col.plan, False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        col(f, out=q)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    npts, lg = n * n, math.log2(n * n)
+    flops = cells * npts * (2.5 * lg + (m + 1) * (5 * lg + 6))
+    col.close()
+    return {"ms_per_batch": ms, "cells_per_s": cells / (ms * 1e-3), "kernel_ms": kernel_ms,
+            "algorithmic_tflops": flops / (kernel_ms * 1e-3) / 1e12,
+            "frac_of_fp32_vector_peak": flops / (kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "workload": f"{cells} cells, two velocity dimensions, N={n}^2 on [-8,8]^2, M={m} angles, "
+                        "Maxwell molecules (Btilde = 1), FP32 + FP64 projection"}
+
+
 def graph_step_run(f_cells, steps: int = 20):
     """The bow-shock workload: a 128 x 128 grid, f resident for every cell
     (FP64, N = 32, the 256-cell batch tiled over the grid), eta1 at the 85th
@@ -508,6 +549,7 @@ def main():
     }
     rec["kinetic"] = kinetic_run(col, f, max(2, args.steps // 2))
     rec["dealiased"] = dealias_run(f, out, max(2, args.steps // 4))
+    rec["maxwell2d"] = maxwell2d_run(max(2, args.steps // 4))
     rec["graph_step"] = graph_step_run(f)
     if args.serve_seconds > 0:
         del out64, col64
