@@ -93,3 +93,33 @@ def test_raw_output_and_fp32_input(precision):
     tol = 1e-5 if precision else 1e-12
     for c in range(3):
         assert spectral.rel_err(q[c], ref[c], loss[c]) <= tol
+
+
+def test_served_2d_requests_match_direct():
+    """2D requests go through the server beside 3D ones: each result equals the
+    direct evaluation of the same plan bit for bit."""
+    import time
+
+    import paper_2505_03360_amd as bz
+    print("case maxwell2d serve", flush=True)
+    srv = bz.Server(arena_bytes=1 << 30, max_inflight=4, n_streams=2)
+    d2 = bz.make_plan2d_desc(32, m=12)
+    d3 = bz.make_plan_desc(n=16, m=8, dir_kind=bz.BZ_DIRS_SPIRAL)
+    f2 = torch.from_numpy(gen.bimaxwellian2d_batch(9, 32, 8.0, seed=21)).cuda()
+    f3 = torch.from_numpy(gen.bimaxwellian_batch(3, 16, 8.0, seed=22)).cuda()
+    q2 = torch.empty((9, 32, 32), dtype=torch.float64, device="cuda")
+    q3 = torch.empty((3, 16, 16, 16), dtype=torch.float64, device="cuda")
+    tickets = [srv.submit(f2, q2, d2), srv.submit(f3, q3, d3)]
+    t0 = time.time()
+    for t in tickets:
+        while True:
+            done, res = srv.poll(t)
+            if done:
+                break
+            assert time.time() - t0 < 60, "request did not finish"
+            time.sleep(0.0005)
+        assert res.state == bz.BZ_REQ_DONE and res.err == 0
+    torch.cuda.synchronize()
+    direct = collider(32, 9, 1, m=12)(f2)
+    assert torch.equal(q2, direct)
+    srv.close()
