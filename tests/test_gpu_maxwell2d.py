@@ -123,3 +123,24 @@ def test_served_2d_requests_match_direct():
     direct = collider(32, 9, 1, m=12)(f2)
     assert torch.equal(q2, direct)
     srv.close()
+
+
+def test_device_count_and_empty_launch():
+    """ncells_dev caps the cells evaluated (rows beyond it keep their contents);
+    ncells = 0 launches nothing."""
+    print("case maxwell2d device count", flush=True)
+    n = 16
+    f = torch.from_numpy(gen.bimaxwellian2d_batch(6, n, 8.0, seed=31)).cuda()
+    col = collider(n, 6, 1, m=8)
+    full = col(f)
+    out = torch.full((6, n, n), -3.0, dtype=torch.float64, device="cuda")
+    cnt = torch.tensor([4], dtype=torch.int32, device="cuda")
+    col(f, ncells=6, ncells_dev=cnt, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:4], full[:4])
+    assert torch.all(out[4:] == -3.0)
+    cnt.zero_()
+    col(f, ncells=6, ncells_dev=cnt, out=out)
+    col(f, ncells=0, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:4], full[:4]) and torch.all(out[4:] == -3.0)
