@@ -106,5 +106,5 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
 bool fused_supported(int n, int fp32);
 bool fused_slices_supported(int n, int slices);
-int fused_default_chunks(int n);
+int fused_default_chunks(int n, int max_cells);
 }  // namespace bz
