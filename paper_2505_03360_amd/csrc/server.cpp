@@ -93,8 +93,9 @@ struct Arena {
 struct PlanKey {
   bz_plan_desc d{};
   std::vector<double> dirs, weights;
+  int chunk_class = 0;  // default direction chunks for the request size (plans differ by it)
   bool operator==(const PlanKey& o) const {
-    return d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
+    return chunk_class == o.chunk_class && d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
            d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
            d.a2 == o.d.a2 && d.precision == o.d.precision && d.transform == o.d.transform &&
            d.project == o.d.project && d.chunks == o.d.chunks && d.slices == o.d.slices &&
@@ -103,9 +104,12 @@ struct PlanKey {
   }
 };
 
-PlanKey make_key(const bz_plan_desc& d) {
+PlanKey make_key(const bz_plan_desc& d, int ncells) {
   PlanKey k;
   k.d = d;
+  // a plan left to pick its own chunks picks them from its capacity: requests
+  // of different size classes get (and cache) different plans
+  if (d.chunks == 0 && d.dim != 2) k.chunk_class = bz::fused_default_chunks(d.n, std::max(1, ncells));
   k.d.max_cells = 0;
   k.d.dirs = nullptr;
   k.d.weights = nullptr;
@@ -420,7 +424,7 @@ bz_status bz_serve_submit(bz_server* s, const bz_request* r, uint64_t* ticket) {
   Req q;
   q.ticket = s->next_ticket++;
   q.r = *r;
-  q.key = make_key(r->plan);
+  q.key = make_key(r->plan, r->ncells);
   q.t_submit = now_ns();
   if (s->submitted == 0) s->t_first_submit = q.t_submit;
   s->submitted += 1;
