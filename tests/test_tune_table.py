@@ -23,9 +23,12 @@ def test_tune_table_selects_strategy(tmp_path):
         assert strategy(24, 64)[0] == bz.BZ_XF_PLAIN            # no fused kernel for n = 24
     finally:
         bz.bz_set_tune_table(None)
-    p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=8, dir_kind=bz.BZ_DIRS_SPIRAL))
-    assert bz.bz_plan_strategy(p) == (bz.BZ_XF_FUSED, 1, 2)
-    bz.bz_plan_destroy(p)
+    # without a table the plan sizes its direction chunks from max_cells
+    for n, cells, chunks in [(16, 1, 4), (16, 256, 4), (16, 512, 2), (16, 2048, 1),
+                             (32, 64, 4), (32, 128, 2), (32, 256, 1)]:
+        p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=cells))
+        assert bz.bz_plan_strategy(p) == (bz.BZ_XF_FUSED, chunks, 2), (n, cells)
+        bz.bz_plan_destroy(p)
 
 
 def test_candidate_set():
