@@ -96,7 +96,11 @@ typedef struct {
   int32_t project;       /* 1: FP64 conservative projection, FP64 output;
                             0: raw Q in the plan precision */
   int32_t max_cells;     /* largest batch the bound workspace must hold */
-  int32_t chunks;        /* fused path: direction chunks per cell (0 = auto) */
+  int32_t chunks;        /* fused path: direction chunks per cell, each a workgroup;
+                            0 = from max_cells (n = 32: 4 up to 64 cells, 2 up to
+                            128, else 1; n = 16: 4 up to 256, 2 up to 512), unless
+                            a tune table has a line for the plan.  Results depend
+                            on the chunk count at FP32 rounding level only */
   int32_t slices;        /* fused path: j3 slices of the LDS transposes, 1 or 2
                             (n = 16 only; n = 32 always uses 2); 0 = auto */
   int32_t dealias;       /* 0: circular convolution (l + m = k mod n);
