@@ -45,48 +45,64 @@ def algorithmic_flops(n: int, m: int):
     return fwd + dirs + loss, dirs + loss
 
 
-def cpu_baseline(f, budget_s: float = 15.0):
-    """Time the FP64 oracle (as it stands) on host cores on the first cells of
-    the batch until ~budget_s of work is done."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
+def oracle_plan(n: int = N, m: int = M, gamma: float = 1.0):
     from oracle import directions, spectral
+    d, w = directions.spiral(m)
+    return spectral.Plan(n, L, spectral.default_R(L), gamma, 4.0, d, w)
+
+
+def cpu_baseline(f, budget_s: float = 15.0, n: int = N, m: int = M, gamma: float = 1.0, what: str = "", plan=None):
+    """Time the FP64 oracle (as it stands) on host cores on the first cells of
+    the batch until ~budget_s of work is done (at least one cell)."""
+    from oracle import spectral
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    d, w = directions.spiral(M)
-    plan = spectral.Plan(N, L, spectral.default_R(L), 1.0, 4.0, d, w)
+    plan = plan or oracle_plan(n, m, gamma)
     spectral.collide(f[0], plan)  # builds the multiplier cache, not timed
     t0 = time.perf_counter()
     done = 0
-    while done < f.shape[0] and time.perf_counter() - t0 < budget_s:
+    while done < f.shape[0] and (done == 0 or time.perf_counter() - t0 < budget_s):
         q = spectral.collide(f[done], plan)
-        spectral.project(q, N, L)
+        spectral.project(q, n, L)
         done += 1
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "cells*Q/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} cells of the {CELLS}-cell N=32 M=32 batch, FP64 naive-DFT oracle + projection, {dt:.1f} s"}
+    what = what or f"the {CELLS}-cell N=32 M=32 batch"
+    return {"value": done / dt, "unit": "cells*Q/s", "cores": int(threads), "kind": "oracle", "cpu": cpu_model(),
+            "nproc": os.cpu_count(),
+            "sample": f"{done} cells of {what}, FP64 naive-DFT oracle + projection, {dt:.1f} s"}
 
 
-def cpu_baseline_fft(f, budget_s: float = 10.0):
+def cpu_baseline_fft(f, budget_s: float = 10.0, n: int = N, m: int = M, gamma: float = 1.0, what: str = "",
+                     plan=None):
     """The oracle's library-FFT evaluation (an FFT per cell and direction, the
     paper's CPU design) with one worker thread per host core over cells, BLAS
     and FFT kept single-threaded inside each worker; about budget_s of work."""
     import concurrent.futures as cf
 
-    from oracle import directions, spectral
+    from oracle import spectral
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
         threadpool_limits = None
     cores = min(os.cpu_count() or 1, 16)
-    d, w = directions.spiral(M)
-    plan = spectral.Plan(N, L, spectral.default_R(L), 1.0, 4.0, d, w)
+    plan = plan or oracle_plan(n, m, gamma)
     spectral.collide_fft(f[0], plan)  # fills the multiplier cache, not timed
 
     def one(c):
-        return spectral.project(spectral.collide_fft(f[c % f.shape[0]], plan), N, L)
+        return spectral.project(spectral.collide_fft(f[c % f.shape[0]], plan), n, L)
 
     ctx = threadpool_limits(1) if threadpool_limits else None
     if ctx:
@@ -102,8 +118,10 @@ def cpu_baseline_fft(f, budget_s: float = 10.0):
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    return {"value": done / dt, "unit": "cells*Q/s", "cores": cores, "kind": "oracle_fft_threads",
-            "sample": f"{done} cells of the N=32 M=32 batch, FP64 library-FFT oracle + projection, "
+    what = what or "the N=32 M=32 batch"
+    return {"value": done / dt, "unit": "cells*Q/s", "cores": cores, "kind": "oracle_fft_threads", "cpu": cpu_model(),
+            "nproc": os.cpu_count(),
+            "sample": f"{done} cells of {what}, FP64 library-FFT oracle + projection, "
                       f"{cores} threads over cells, {dt:.1f} s"}
 
 
@@ -192,7 +210,7 @@ def serving_run(seconds: float, seed: int = 5):
                         "FP32 + FP64 projection, 24 GiB arena"}
 
 
-def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.0, 0.5, 1.0)):
+def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.0, 0.5, 1.0), cpu: bool = True):
     """Precision sweep: N in {32, 48}, M in {32, 64}, gamma in {0, 0.5, 1};
     FP32 (fused at N=32, plain passes at N=48) and FP64 plain on the same
     cells (64 seeded shock cells tiled to `cells`).  Reports time per batch,
@@ -244,6 +262,14 @@ def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.
                 rec["moment_drift_projected_fp64"] = drift(res["fp64"])
                 rec["fp32_cells_per_s"] = cells / (rec["fp32_ms_per_batch"] * 1e-3)
                 rec["fp64_cells_per_s"] = cells / (rec["fp64_ms_per_batch"] * 1e-3)
+                if cpu and gamma == gammas[-1]:
+                    # the oracle's cost per cell does not depend on gamma: timed once per (N, M)
+                    fh = base.cpu().numpy()
+                    what = f"the N={n} M={m} gamma={gamma} sweep cells"
+                    plan = oracle_plan(n, m, gamma)
+                    rec["cpu_baseline"] = cpu_baseline(fh, 4.0, n, m, gamma, what, plan)
+                    rec["cpu_baseline_fft"] = cpu_baseline_fft(fh, 4.0, n, m, gamma, what, plan)
+                    del plan
                 del res
                 torch.cuda.empty_cache()
                 print(json.dumps(rec), flush=True)
@@ -467,7 +493,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.sweep:
-        sweep(ns=args.sweep_n, ms=args.sweep_m, gammas=args.sweep_gamma)
+        sweep(ns=args.sweep_n, ms=args.sweep_m, gammas=args.sweep_gamma, cpu=not args.no_cpu)
         return
     f_np = gen.shock_batch(CELLS, N, L, seed=2)
     f = torch.from_numpy(f_np).cuda()
@@ -557,8 +583,9 @@ def main():
         rec["serving"] = serving_run(args.serve_seconds)
         rec["p99_latency_ms"] = rec["serving"]["p99_ms"]
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(f_np, args.cpu_budget)
-        rec["cpu_baseline_fft"] = cpu_baseline_fft(f_np, min(args.cpu_budget, 10.0))
+        plan = oracle_plan()
+        rec["cpu_baseline"] = cpu_baseline(f_np, args.cpu_budget, plan=plan)
+        rec["cpu_baseline_fft"] = cpu_baseline_fft(f_np, min(args.cpu_budget, 10.0), plan=plan)
     print(json.dumps(rec))
 
 

@@ -174,7 +174,7 @@ def multipliers(plan: Plan, p: int):
     P3 = K3 - s * e[2]
     r = np.sqrt(P1 * P1 + P2 * P2 + P3 * P3)
     res = (phi(s, plan.R, plan.gamma), psi(r, plan.R))
-    if plan.n <= 32:
+    if 16 * plan.n ** 3 * plan.m <= 1 << 29:  # keep all directions when they fit in 512 MiB
         plan._cache[key] = res
     return res
 
