@@ -210,6 +210,38 @@ def serving_run(seconds: float, seed: int = 5):
                         "FP32 + FP64 projection, 24 GiB arena"}
 
 
+def peak_probe(blocks: int = 256 * 8, iters: int = 2048, reps: int = 5):
+    """Issue rate of unpacked FP32 VALU operations (the instruction forms the
+    collision kernels are built with) over the whole chip, from the probe
+    library built beside libbz.so; one JSON line per operation."""
+    import ctypes
+
+    import torch
+
+    lib_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_03360_amd", "libbz_peak.so")
+    if not os.path.exists(lib_path):
+        raise RuntimeError(f"{lib_path} is not built: run paper_2505_03360_amd/build.py")
+    lib = ctypes.CDLL(lib_path)
+    lib.bz_peak_valu.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                                       ctypes.POINTER(ctypes.c_double)]
+    lib.bz_peak_valu.restype = ctypes.c_int
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    prop = torch.cuda.get_device_properties(0)
+    cus = prop.multi_processor_count
+    for kind, name, flop in ((0, "v_fma_f32", 2), (3, "v_fmac_f32", 2), (1, "v_add_f32", 1), (2, "v_mul_f32", 1)):
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        rc = lib.bz_peak_valu(kind, blocks, iters, reps, ctypes.c_void_p(out.data_ptr()),
+                              ctypes.byref(rate), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"bz_peak_valu({name}) failed: {rc}")
+        torch.cuda.synchronize()
+        ops = rate.value / flop  # wave-lane operations per second
+        print(json.dumps({"probe": name, "tflops": rate.value / 1e12, "ms": ms.value, "cus": cus,
+                          "device": prop.name, "blocks": blocks, "threads": 256, "iters": iters,
+                          "lane_ops_per_cu_per_cycle_at_2p4GHz": ops / cus / 2.4e9,
+                          "finite": bool(torch.isfinite(out).all())}))
+
+
 def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.0, 0.5, 1.0), cpu: bool = True):
     """Precision sweep: N in {32, 48}, M in {32, 64}, gamma in {0, 0.5, 1};
     FP32 (fused at N=32, plain passes at N=48) and FP64 plain on the same
@@ -477,6 +509,8 @@ def main():
     ap.add_argument("--sweep-n", type=int, nargs="*", default=[32, 48])
     ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
     ap.add_argument("--sweep-gamma", type=float, nargs="*", default=[0.0, 0.5, 1.0])
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only measure the unpacked FP32 VALU issue rate (one JSON line per operation)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -492,6 +526,9 @@ def main():
     import paper_2505_03360_amd as bz
 
     torch.cuda.set_device(0)
+    if args.peak_probe:
+        peak_probe()
+        return
     if args.sweep:
         sweep(ns=args.sweep_n, ms=args.sweep_m, gammas=args.sweep_gamma, cpu=not args.no_cpu)
         return

@@ -251,3 +251,16 @@ def test_plan2d_refused_by_three_dimensional_entry_points():
         bz.bz_pr222_stage1(p, d, 1, 0, 1, 0, 2, 0)
     assert e.value.code == bz.BZ_ERR_UNSUPPORTED
     bz.bz_plan_destroy(p)
+
+
+def test_peak_probe_library_exports_its_entry():
+    """The issue-rate probe is a library of its own beside libbz.so (built by the
+    same build step); it loads without a GPU and exports bz_peak_valu."""
+    import ctypes
+    import os
+
+    import paper_2505_03360_amd.build as b
+    if not os.path.exists(b.PEAK_LIB):
+        pytest.skip("libbz_peak.so not built")
+    lib = ctypes.CDLL(b.PEAK_LIB)
+    assert hasattr(lib, "bz_peak_valu")
