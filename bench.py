@@ -31,7 +31,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM-side bytes per launch of k_collide_fused<32,2> on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain
 # 256 MiB copy needs); set to None whenever the kernel changes until re-measured.
-FUSED_TRAFFIC_BYTES = (230741 * 2.0 + 97280 * 1.0) * 1024
+FUSED_TRAFFIC_BYTES = (187127 * 2.0 + 70656 * 1.0) * 1024
 
 
 def algorithmic_flops(n: int, m: int):
