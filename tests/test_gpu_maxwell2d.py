@@ -144,3 +144,26 @@ def test_device_count_and_empty_launch():
     col(f, ncells=0, out=out)
     torch.cuda.synchronize()
     assert torch.equal(out[:4], full[:4]) and torch.all(out[4:] == -3.0)
+
+
+def test_benchmarked_batch_sampled():
+    """The benchmarked 2D launch (4096 cells, N = 64, M = 32, FP32 + FP64
+    projection, seed 11): sampled cells against the oracle, the four invariants
+    of every cell conserved after the projection."""
+    print("case maxwell2d 4096 cells", flush=True)
+    n, m, cells = 64, 32, 4096
+    f = gen.bimaxwellian2d_batch(cells, n, 8.0, seed=11)
+    col = collider(n, cells, 1, m=m)
+    q = col(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    q = q.cpu().numpy()
+    sample = [0, 1, 777, 2048, 4031, 4095]
+    ref, loss = oracle(f[sample], n, m)
+    for i, c in enumerate(sample):
+        err = spectral.rel_err(q[c], ref[i], loss[i])
+        print(f"  cell {c}: err {err:.3e}", flush=True)
+        assert err <= 1e-5
+    C = m2.moment_matrix(n, 8.0)
+    mom = np.abs(q.reshape(cells, -1) @ C.T)
+    scale = np.abs(q.reshape(cells, -1)) @ np.abs(C.T)
+    assert (mom / scale).max() <= 1e-12
