@@ -26,6 +26,10 @@ constexpr size_t kStatusBytes = 256;
 // stage-A volume per cell in the workspace, so n = 48 (0.9 MB per volume)
 // takes fewer than the smaller grids.
 constexpr int plain_chunk(int n) { return n <= 32 ? 8 : 4; }
+// Two-dimensional plans keep a cell's spectrum in the workspace from n = 32
+// up (the LDS then holds one transpose buffer per cell: twice the waves per
+// CU); at n = 16 it stays in the LDS, which does not limit occupancy there.
+constexpr bool spectrum2d_in_workspace(int n) { return n >= 32; }
 
 // Workspace regions of a bound plan, each [capacity][...].
 struct WsLayout {

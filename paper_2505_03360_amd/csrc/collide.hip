@@ -36,9 +36,12 @@
 //          resampled back onto the n grid.
 #include "bz_internal.hpp"
 #include "fft.hpp"
+#include "gptr.hpp"
 #include "kinetic.hpp"
 
 using bzk::cx;
+using bzk::gptr;
+using bzk::opaque_global;
 
 namespace {
 
@@ -148,23 +151,6 @@ __global__ __launch_bounds__(256) void k_fwd3(PlainArgs<T> a) {
 template <typename T>
 __device__ __forceinline__ T load_f(const void* f, int f_fp32, size_t i) {
   return f_fp32 ? T(static_cast<const float*>(f)[i]) : T(static_cast<const double*>(f)[i]);
-}
-
-// Global-address-space pointer whose value the compiler cannot see through:
-// per-pass load bases stay in the pass loop (the compiler would otherwise
-// hoist every base + k*stride address out of it, 2 registers each), and the
-// loads remain global (not flat) loads with immediate offsets.
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-using gptr = const __attribute__((address_space(1))) T*;
-#else
-template <typename T>
-using gptr = const T*;
-#endif
-template <typename T>
-__device__ __forceinline__ gptr<T> opaque_global(const T* p) {
-  asm volatile("" : "+v"(p));
-  return (gptr<T>)p;
 }
 
 // Streaming (non-temporal) access to a complex value: for data touched once

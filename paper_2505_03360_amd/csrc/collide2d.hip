@@ -13,17 +13,23 @@
 // One 64-lane wave holds 64/n cells; lane r of a cell owns row k1 = r of the
 // spectrum and, after the transpose, column j2 = r of the physical grid:
 //   forward: column i2 = r of f along i1, LDS transpose, row k1 = r along i2;
-//            fhat rows stay in LDS ([k1][k2], each lane reads only its own);
+//            from n = 32 up fhat goes to the cell's workspace slot ([k2][k1]:
+//            the n lanes of a cell write and read consecutive entries, each
+//            lane only its own row), which keeps the LDS to one transpose
+//            buffer per cell; at n = 16 the rows stay in LDS;
 //   pass:    row k1 = r: X along k2 -> j2, LDS transpose, column j2 = r along
 //            k1 -> j1, products into the lane's n accumulators.
-// Layouts: f, q [i1][i2] (i2 fastest), multipliers [pass][k2][k1] (lanes on
+// Layouts: f, q [i1][i2] (i2 fastest), multipliers and fhat [k2][k1] (lanes on
 // k1 read consecutive entries).
 #include "bz_internal.hpp"
 #include "fft.hpp"
+#include "gptr.hpp"
 
 namespace {
 
 using bzk::cx;
+using bzk::gptr;
+using bzk::opaque_global;
 
 struct Args2D {
   int ncells;
@@ -34,6 +40,8 @@ struct Args2D {
   int scatter;
   const void* mult;  // [pass][k2][k1] pairs in the plan precision
   const void* w;     // [pass] weights, the loss scale last
+  void* fs;          // workspace: fhat of compact cell c at fs + c * fs_stride, [k2][k1]
+  size_t fs_stride;  // elements (complex, plan precision) per cell
   int m1;
   double C, dv;
   double ginv[16];   // (C C^T)^-1 of the four invariants
@@ -62,13 +70,18 @@ template <typename T, int N>
 __global__ __launch_bounds__(64, 2) void k_collide2d(Args2D a) {
   constexpr int G = 64 / N;  // cells per wave
   constexpr int P = N + 1;   // LDS row pitch
+  constexpr bool kWs = bz::spectrum2d_in_workspace(N);  // else the spectrum rows stay in LDS
   __shared__ cx<T> tr[G][N][P];
-  __shared__ cx<T> fs[G][N][P];
+  __shared__ cx<T> fsl[kWs ? 1 : G][kWs ? 1 : N][kWs ? 1 : P];
   const int lane = threadIdx.x, g = lane / N, r = lane % N;
   const int cell = blockIdx.x * G + g;
   const bool live = cell < live_cells2d(a.ncells, a.ncells_dev);
   const long row = live ? (a.idx ? long(a.idx[cell]) : long(cell)) : 0;
   const size_t fbase = size_t(row) * N * N;
+  // the cell's spectrum slot: the workspace holds the launched cells, not the
+  // idle tail of the last wave, so idle lanes point at cell 0's slot (present
+  // whenever a launch happens), never write it, and discard what they read
+  cx<T>* const fsg = static_cast<cx<T>*>(a.fs) + (live ? size_t(cell) * a.fs_stride : 0) + r;
   cx<T> x[N];
   // forward: column i2 = r along i1, then row k1 = r along i2
 #pragma unroll
@@ -85,7 +98,14 @@ __global__ __launch_bounds__(64, 2) void k_collide2d(Args2D a) {
   bzk::fft<N, -1>(x);
   const T scale = T(1) / T(N * N);
 #pragma unroll
-  for (int k2 = 0; k2 < N; ++k2) fs[g][r][k2] = cx<T>{x[k2].x * scale, x[k2].y * scale};
+  for (int k2 = 0; k2 < N; ++k2) {
+    const cx<T> v{x[k2].x * scale, x[k2].y * scale};
+    if constexpr (kWs) {
+      if (live) fsg[size_t(k2) * N] = v;
+    } else {
+      fsl[g][r][k2] = v;
+    }
+  }
   T acc[N];
 #pragma unroll
   for (int j1 = 0; j1 < N; ++j1) acc[j1] = T(0);
@@ -93,11 +113,26 @@ __global__ __launch_bounds__(64, 2) void k_collide2d(Args2D a) {
   const T* wt = static_cast<const T*>(a.w);
   for (int p = 0; p < a.m1; ++p) {
     __syncthreads();  // the previous pass (or the forward) has read tr
-    const cx<T>* M = mult + size_t(p) * N * N + r;
+    // opaque per-pass bases: the n addresses of each row are formed here,
+    // not hoisted out of the pass loop (2 registers each)
+    const gptr<cx<T>> M = opaque_global(mult + size_t(p) * N * N + r);
+    const gptr<cx<T>> F0 = opaque_global(fsg);
+    // in groups of 16 (bounded loads in flight)
 #pragma unroll
-    for (int k2 = 0; k2 < N; ++k2) {
-      const cx<T> m = M[size_t(k2) * N], F = fs[g][r][k2];
-      x[k2] = cx<T>{m.x * F.x - m.y * F.y, m.x * F.y + m.y * F.x};
+    for (int h = 0; h < N; h += 16) {
+#pragma unroll
+      for (int k2 = h; k2 < h + 16; ++k2) {
+        const cx<T> m = M[size_t(k2) * N];
+        cx<T> F;
+        if constexpr (kWs) {
+          const cx<T> Fl = F0[size_t(k2) * N];  // idle lanes read the slot of cell 0
+          F = live ? Fl : cx<T>{T(0), T(0)};
+        } else {
+          F = fsl[g][r][k2];
+        }
+        x[k2] = cx<T>{m.x * F.x - m.y * F.y, m.x * F.y + m.y * F.x};
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     bzk::fft<N, 1>(x);  // along k2 -> j2, row k1 = r
 #pragma unroll
@@ -111,11 +146,18 @@ __global__ __launch_bounds__(64, 2) void k_collide2d(Args2D a) {
     bzk::fft<N, 1>(x);  // along k1 -> j1, column j2 = r
     const T wp = wt[p];
     if (p == a.m1 - 1) {
+      // loss pass with the input f (opaque base: the n row addresses are not
+      // held across the pass loop; idle lanes read row 0 and discard it)
+      auto loss = [&](auto fp) {
 #pragma unroll
-      for (int j1 = 0; j1 < N; ++j1) {
-        const T fj = live ? load_f2d<T>(a, fbase + size_t(j1) * N + r) : T(0);
-        acc[j1] -= (wp * fj - x[j1].y) * x[j1].x;
-      }
+        for (int j1 = 0; j1 < N; ++j1) {
+          const T fl = T(fp[size_t(j1) * N]);
+          const T fj = live ? fl : T(0);
+          acc[j1] -= (wp * fj - x[j1].y) * x[j1].x;
+        }
+      };
+      if (a.f_fp32) loss(opaque_global(static_cast<const float*>(a.f) + fbase + r));
+      else loss(opaque_global(static_cast<const double*>(a.f) + fbase + r));
     } else {
 #pragma unroll
       for (int j1 = 0; j1 < N; ++j1) acc[j1] += wp * x[j1].x * x[j1].y;
@@ -192,6 +234,8 @@ bz_status launch_collide2d(const bz_plan* p, const Binding& b, const void* f, in
   a.scatter = scatter;
   a.mult = b.tables;
   a.w = static_cast<const char*>(b.tables) + p->table_w_off;
+  a.fs = static_cast<char*>(b.ws) + b.lay.fh_off;
+  a.fs_stride = b.lay.fh_cell / (p->fp32 ? 8 : 16);
   a.m1 = p->m1;
   a.C = p->C;
   a.dv = p->dv;

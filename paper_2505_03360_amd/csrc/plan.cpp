@@ -346,7 +346,7 @@ void layout2d(bz_plan* p) {
   p->table_w_off = p->table_mult_bytes;
   p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
   p->ws = WsLayout{};
-  p->ws.fh_cell = 256;
+  p->ws.fh_cell = spectrum2d_in_workspace(p->n) ? align256(p->npts * 2 * es) : 256;  // the cell's spectrum, [k2][k1]
   p->ws_fixed = kStatusBytes;
   p->ws_per_cell = p->ws.fh_cell;
 }
