@@ -212,8 +212,9 @@ def serving_run(seconds: float, seed: int = 5):
 
 def peak_probe(blocks: int = 256 * 8, iters: int = 2048, reps: int = 5):
     """Issue rate of unpacked FP32 VALU operations (the instruction forms the
-    collision kernels are built with) over the whole chip, from the probe
-    library built beside libbz.so; one JSON line per operation."""
+    collision kernels are built with) and LDS read and write bandwidth over the
+    whole chip, from the probe library built beside libbz.so; one JSON line per
+    operation."""
     import ctypes
 
     import torch
@@ -239,6 +240,20 @@ def peak_probe(blocks: int = 256 * 8, iters: int = 2048, reps: int = 5):
         print(json.dumps({"probe": name, "tflops": rate.value / 1e12, "ms": ms.value, "cus": cus,
                           "device": prop.name, "blocks": blocks, "threads": 256, "iters": iters,
                           "lane_ops_per_cu_per_cycle_at_2p4GHz": ops / cus / 2.4e9,
+                          "finite": bool(torch.isfinite(out).all())}))
+    lib.bz_peak_lds.argtypes = lib.bz_peak_valu.argtypes
+    lib.bz_peak_lds.restype = ctypes.c_int
+    for kind, name in ((0, "ds_read2st64_b64"), (1, "ds_write2st64_b64"), (2, "ds_write_b32"),
+                       (3, "ds_write_b64"), (4, "ds_write_b128")):
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        rc = lib.bz_peak_lds(kind, blocks, iters, reps, ctypes.c_void_p(out.data_ptr()),
+                             ctypes.byref(rate), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"bz_peak_lds({name}) failed: {rc}")
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": name, "tb_per_s": rate.value / 1e12, "ms": ms.value, "cus": cus,
+                          "blocks": blocks, "threads": 256, "iters": iters,
+                          "bytes_per_cu_per_cycle_at_2p4GHz": rate.value / cus / 2.4e9,
                           "finite": bool(torch.isfinite(out).all())}))
 
 
