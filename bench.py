@@ -327,7 +327,7 @@ def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.
 def kinetic_run(col, f, steps: int):
     """The per-cell kinetic steps on the same batch: macroscopic fields + L1
     distance (bz_cell_moments), one penalised IMEX step (bz_imex_euler,
-    eq. 1002) fused with the collision evaluation, the ES-BGK operator and its
+    eq. (4.24)) fused with the collision evaluation, the ES-BGK operator and its
     IMEX step.  Times from HIP events on the current stream; compulsory bytes
     per cell: 8n (moments), 16n (ES-BGK: f in, Q out), 24n (ES-BGK IMEX: f and
     the transport term in, f_out out)."""
@@ -382,7 +382,7 @@ def kinetic_run(col, f, steps: int):
             "esbgk_collide_compulsory_GB_s": cells * 16 * N ** 3 / (es_ms * 1e-3) / 1e9,
             "esbgk_imex_ms": esi_ms,
             "esbgk_imex_compulsory_GB_s": cells * 24 * N ** 3 / (esi_ms * 1e-3) / 1e9,
-            "workload": f"{cells} cells N=32; M=32 FP32 collision + FP64 IMEX (eq. 1002), dt=0.01, eps=0.01; "
+            "workload": f"{cells} cells N=32; M=32 FP32 collision + FP64 IMEX (eq. (4.24)), dt=0.01, eps=0.01; "
                         "ES-BGK beta=-1/2, mu0=1"}
 
 

@@ -254,7 +254,7 @@ bz_status bz_cell_moments(int32_t n, double L, const void* f, int32_t f_dtype, c
 
 /*
  * One step of the penalised first-order IMEX scheme of the Boltzmann layer
- * (Sec. 4.4, eq. 1002, after Filbet and Jin), fused with the evaluation of
+ * (Sec. 4.4, eq. (4.24), after Filbet and Jin), fused with the evaluation of
  * Q(f^n) by `plan`:
  *   g = f^n - dt tr,  U^{n+1} = int (1, v, |v|^2) g  (Q and P conserve them),
  *   beta = 2 pi rho^{n+1},  P(h) = beta (M[h] - h),

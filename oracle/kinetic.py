@@ -13,7 +13,7 @@ velocity are the grid sums times dv^3.
   maxwellian   M(v) = rho (2 pi T)^(-3/2) exp(-|v - u|^2 / (2 T)) (Sec. 2).
   l1_distance  || f - M[f] ||_{L1_v}, the quantity compared with delta_0 in
                the kinetic-to-fluid criterion (Sec. 3.3).
-  imex_euler   the penalised scheme of Sec. 4.4 (eq. 1002): with the transport
+  imex_euler   the penalised scheme of Sec. 4.4 (eq. (4.24)): with the transport
                term tr = v . grad_x f^n given,
                  g = f^n - dt tr,  U^{n+1} = int phi g (phi = 1, v, |v|^2),
                  beta = 2 pi rho^{n+1},  P(h) = beta (M[h] - h),
@@ -83,7 +83,7 @@ def maxwellian_of_conserved(U, n: int, L: float) -> tuple[np.ndarray, float]:
 
 
 def imex_combine(f: np.ndarray, tr: np.ndarray, q: np.ndarray, dt: float, eps: float, L: float) -> np.ndarray:
-    """The update of eq. 1002 given Q(f^n) (any array q) and the transport term."""
+    """The update of eq. (4.24) given Q(f^n) (any array q) and the transport term."""
     n = f.shape[0]
     g = f - dt * tr
     M1, rho1 = maxwellian_of_conserved(conserved(g, n, L), n, L)
@@ -96,7 +96,7 @@ def imex_combine(f: np.ndarray, tr: np.ndarray, q: np.ndarray, dt: float, eps: f
 
 def imex_euler(f: np.ndarray, tr: np.ndarray, dt: float, eps: float, plan: spectral.Plan,
                project: bool = True) -> np.ndarray:
-    """One penalised first-order IMEX step of the Boltzmann layer (eq. 1002),
+    """One penalised first-order IMEX step of the Boltzmann layer (eq. (4.24)),
     Q(f^n) from the spectral oracle (projected on the invariants if asked)."""
     q = spectral.collide(f, plan)
     if project:

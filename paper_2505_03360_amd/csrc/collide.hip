@@ -457,7 +457,7 @@ struct FusedArgs {
   double* q;
   int32_t* status;   // set to 1 when a non-finite value is written
   int zero;           // 0 at run time: keeps the status store a per-lane (vector) store
-  int imex;           // write the IMEX update of eq. 1002 instead of Q (projection epilogue only;
+  int imex;           // write the IMEX update of eq. (4.24) instead of Q (projection epilogue only;
                       // selects the IMEX instantiation of the kernel)
   bzk::ImexDev im;
 };
@@ -917,7 +917,7 @@ struct ProjArgs {
   int project;  // 1: FP64 projection, FP64 output
   void* q;
   int q_fp32;   // output type when project == 0
-  int imex;     // write the IMEX update of eq. 1002 (FP64) instead of Q
+  int imex;     // write the IMEX update of eq. (4.24) (FP64) instead of Q
   bzk::ImexDev im;
   int32_t* status;  // set to 1 when a non-finite value is written
   int zero;         // 0 at run time (per-lane store address)

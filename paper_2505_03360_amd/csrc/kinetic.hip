@@ -1,7 +1,7 @@
 // Per-cell reductions over the velocity grid on gfx950, FP64: macroscopic
 // fields and the L1 distance of the kinetic-to-fluid criterion (Sec. 2 and
 // 3.3), and the parameters of the penalised IMEX update of the Boltzmann layer
-// (Sec. 4.4, eq. 1002).
+// (Sec. 4.4, eq. (4.24)).
 //
 // One workgroup of 1024 threads per cell (16 waves per CU keep enough loads in
 // flight for these HBM-bound sums).  Each thread accumulates a strided subset

@@ -1,5 +1,5 @@
 // Per-cell kinetic quantities shared by the IMEX kernels: the Maxwellians of
-// the penalised update (Sec. 4.4, eq. 1002) are evaluated pointwise in the
+// the penalised update (Sec. 4.4, eq. (4.24)) are evaluated pointwise in the
 // epilogues of the collision kernels from parameters one reduction kernel
 // computes per cell.
 #pragma once
@@ -23,7 +23,7 @@ struct ImexDev {
   double dt;
 };
 
-// f^{n+1} at one velocity node (eq. 1002 with P(h) = beta (M[h] - h)):
+// f^{n+1} at one velocity node (eq. (4.24) with P(h) = beta (M[h] - h)):
 //   (eps (f - dt tr) + dt (Q - beta (M^n - f)) + beta dt M^{n+1}) / (eps + beta dt)
 __device__ __forceinline__ double imex_point(const double* par, double q, double f, double tr, double eps,
                                              double dt, double v1, double v2, double v3) {
