@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_rsC(PlainArgs<T> a) {
   for (int j1 = 0; j1 < NO; ++j1) out[size_t(j1) * NO * NO] = x[j1].x;
 }
 
-// ------------------------------------------------------------------ chunked plain passes (FP32)
+// ------------------------------------------------------------------ chunked plain passes
 // Two kernels per chunk of directions, for the sizes and strategies without a
 // fused kernel:
 //   k_pA:  thread (cell, k2, k1) loads its fhat pencil along k3 once and, for
@@ -1016,17 +1016,17 @@ __global__ __launch_bounds__(kProjThreads) void k_project(ProjArgs a) {
 }
 
 // Projection of a plane-major accumulator acc[cell][j3][j1][j2] (one chunk,
-// FP32, from the chunked plain passes).  Moments are summed in the
+// in the plan precision A, from the chunked plain passes).  Moments are summed in the
 // accumulator's own order (fixed); the output [j1][j2][j3] is written through
 // LDS tiles of 64 (j1, j2) columns so that both the reads and the writes are
 // coalesced.
-template <int N>
+template <int N, typename A>
 __global__ __launch_bounds__(kProjThreads) void k_project_pm(ProjArgs a) {
   constexpr int N2 = N * N, N3 = N2 * N, TC = 64;
   static_assert(N2 % TC == 0, "column tiles cover the plane");
   const int c = blockIdx.x;
   if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const float* acc = static_cast<const float*>(a.acc) + size_t(c) * a.acc_stride;
+  const A* acc = static_cast<const A*>(a.acc) + size_t(c) * a.acc_stride;
   const size_t row = a.scatter ? size_t(a.idx[c]) : size_t(c);
   const size_t frow = a.idx ? size_t(a.idx[c]) : size_t(c);
   const int t = threadIdx.x;
@@ -1080,24 +1080,28 @@ __global__ __launch_bounds__(kProjThreads) void k_project_pm(ProjArgs a) {
 }
 
 // Launch the projection of a plan's accumulator (plane-major for the chunked
-// FP32 passes); false for a grid size without an instantiation.
+// plain passes); false for a grid size without an instantiation.
 bool launch_project(int n, bool plane_major, const ProjArgs& pa, int ncells, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(ncells)), block(kProjThreads);
   switch (n) {
     case 16:
-      if (plane_major) hipLaunchKernelGGL(k_project_pm<16>, grid, block, 0, s, pa);
+      if (plane_major && pa.acc_fp32) hipLaunchKernelGGL((k_project_pm<16, float>), grid, block, 0, s, pa);
+      else if (plane_major) hipLaunchKernelGGL((k_project_pm<16, double>), grid, block, 0, s, pa);
       else hipLaunchKernelGGL(k_project<16>, grid, block, 0, s, pa);
       return true;
     case 24:
-      if (plane_major) hipLaunchKernelGGL(k_project_pm<24>, grid, block, 0, s, pa);
+      if (plane_major && pa.acc_fp32) hipLaunchKernelGGL((k_project_pm<24, float>), grid, block, 0, s, pa);
+      else if (plane_major) hipLaunchKernelGGL((k_project_pm<24, double>), grid, block, 0, s, pa);
       else hipLaunchKernelGGL(k_project<24>, grid, block, 0, s, pa);
       return true;
     case 32:
-      if (plane_major) hipLaunchKernelGGL(k_project_pm<32>, grid, block, 0, s, pa);
+      if (plane_major && pa.acc_fp32) hipLaunchKernelGGL((k_project_pm<32, float>), grid, block, 0, s, pa);
+      else if (plane_major) hipLaunchKernelGGL((k_project_pm<32, double>), grid, block, 0, s, pa);
       else hipLaunchKernelGGL(k_project<32>, grid, block, 0, s, pa);
       return true;
     case 48:
-      if (plane_major) hipLaunchKernelGGL(k_project_pm<48>, grid, block, 0, s, pa);
+      if (plane_major && pa.acc_fp32) hipLaunchKernelGGL((k_project_pm<48, float>), grid, block, 0, s, pa);
+      else if (plane_major) hipLaunchKernelGGL((k_project_pm<48, double>), grid, block, 0, s, pa);
       else hipLaunchKernelGGL(k_project<48>, grid, block, 0, s, pa);
       return true;
     default:
@@ -1120,7 +1124,7 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   const long threads = long(ncells) * N * N;
   const dim3 grid(unsigned((threads + 255) / 256)), block(256);
   a.m1 = m1;
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (bz::plain_chunked(N, sizeof(T) == 4)) {
     constexpr int NG = N / (4 * plain_planes_per_wave<N>());
     const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
     for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
@@ -1432,7 +1436,8 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   }
   if (st != BZ_OK) return st;
   if (timed) (void)hipEventRecord(pm->ev[2], s);
-  if (!fused_projection && !launch_project(p->n, p->fp32 && p->transform == BZ_XF_PLAIN, pa, ncells, s))
+  if (!fused_projection &&
+      !launch_project(p->n, p->transform == BZ_XF_PLAIN && plain_chunked(p->n, p->fp32), pa, ncells, s))
     return fail(BZ_ERR_UNSUPPORTED, "projection: n=%d", p->n);
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);
