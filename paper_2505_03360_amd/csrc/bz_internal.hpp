@@ -22,14 +22,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Every workspace starts with a status region: int32 word 0 is set by the
 // output epilogues when they write a non-finite value.
 constexpr size_t kStatusBytes = 256;
-// Directions per launch pair of the chunked plain FP32 path: each keeps one
-// stage-A volume per cell in the workspace, so n = 48 (0.9 MB per volume)
-// takes fewer than the smaller grids.
+// Directions per launch pair of the chunked plain path: each keeps one
+// stage-A volume per cell in the workspace, so n = 48 (0.9 MB per volume in
+// FP32, 1.8 MB in FP64) takes fewer than the smaller grids.
 constexpr int plain_chunk(int n) { return n <= 32 ? 8 : 4; }
-// The chunked kernels serve FP32 at every size and FP64 up to n = 32 (at
-// n = 48 an FP64 chunk would need 150 KB of LDS per workgroup and 7 MB of
-// workspace per cell); other FP64 plans take three passes per direction.
-constexpr bool plain_chunked(int n, bool fp32) { return fp32 || n <= 32; }
 // Two-dimensional plans keep a cell's spectrum in the workspace from n = 32
 // up (the LDS then holds one transpose buffer per cell: twice the waves per
 // CU); at n = 16 it stays in the LDS, which does not limit occupancy there.

@@ -74,14 +74,13 @@ struct PlainArgs {
   const int32_t* ncells_dev;
   cx<T>* fh;  // [cell][k2][k3][k1]
   cx<T>* y;   // [cell][...]
-  T* acc;     // [cell][chunks][j1][j2][j3]
+  T* acc;     // [cell][...]: plane-major [j3][j1][j2] (chunked passes) or [j1][j2][j3] (resampling)
   size_t fh_stride, y_stride, acc_stride;  // elements per cell
   const cx<T>* mult;  // [pass][k2][k3][k1]
   const T* w;         // [pass]
   int pass;
-  int first;
-  int loss;  // this pass is the loss pass (the last one)
-  int m1;    // passes (directions + the loss pass)
+  int first;  // the chunk starting at pass 0 (initialises the accumulator)
+  int m1;     // passes (directions + the loss pass)
 };
 
 // ------------------------------------------------------------------ forward
@@ -148,11 +147,6 @@ __global__ __launch_bounds__(256) void k_fwd3(PlainArgs<T> a) {
   for (int k3 = 0; k3 < N; ++k3) fh[size_t(k3) * N] = cx<T>{x[k3].x * scale, x[k3].y * scale};
 }
 
-template <typename T>
-__device__ __forceinline__ T load_f(const void* f, int f_fp32, size_t i) {
-  return f_fp32 ? T(static_cast<const float*>(f)[i]) : T(static_cast<const double*>(f)[i]);
-}
-
 // Streaming (non-temporal) access to a complex value: for data touched once
 // per launch, so that it does not evict what the launch re-reads from L2.
 template <typename T>
@@ -170,32 +164,9 @@ __device__ __forceinline__ cx<T> nt_load(const cx<T>* p) {
   return cx<T>{w.x, w.y};
 }
 
-// ------------------------------------------------------------------ plain passes
-// pass A: X = (alpha + i alpha') fhat, inverse along k3; thread (cell, k2, k1)
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_dirA(PlainArgs<T> a) {
-  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int c = int(g / (N * N));
-  const int rem = int(g % (N * N));
-  if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const int k2 = rem / N, k1 = rem % N;
-  const size_t off = size_t(k2) * N * N + k1;
-  const cx<T>* fh = a.fh + c * a.fh_stride + off;
-  const cx<T>* mu = a.mult + size_t(a.pass) * N * N * N + off;
-  cx<T> x[N];
-#pragma unroll
-  for (int k3 = 0; k3 < N; ++k3) {
-    const cx<T> F = fh[size_t(k3) * N];
-    const cx<T> M = mu[size_t(k3) * N];
-    x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
-  }
-  bzk::fft<N, 1>(x);
-  cx<T>* y = a.y + c * a.y_stride + off;
-#pragma unroll
-  for (int j3 = 0; j3 < N; ++j3) y[size_t(j3) * N] = x[j3];
-}
-
-// pass B: inverse along k2; y[cell][k2][j3][k1] -> y[cell][j2][j3][k1]; thread (cell, j3, k1)
+// ------------------------------------------------------------------ pencil pass along k2
+// inverse along k2 in place (the middle pass of the spectral resampling);
+// y[cell][k2][j3][k1] -> y[cell][j2][j3][k1]; thread (cell, j3, k1)
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_dirB(PlainArgs<T> a) {
   const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -210,39 +181,6 @@ __global__ __launch_bounds__(256) void k_dirB(PlainArgs<T> a) {
   bzk::fft<N, 1>(x);
 #pragma unroll
   for (int j2 = 0; j2 < N; ++j2) y[size_t(j2) * N * N] = x[j2];
-}
-
-// pass C: inverse along k1 and accumulate w Re Im into acc[cell][j1][j2][j3];
-// thread (cell, j2, j3)
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_dirC(PlainArgs<T> a) {
-  const long g = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int c = int(g / (N * N));
-  const int rem = int(g % (N * N));
-  if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const int j2 = rem / N, j3 = rem % N;
-  const cx<T>* y = a.y + c * a.y_stride + size_t(j2) * N * N + size_t(j3) * N;
-  cx<T> x[N];
-#pragma unroll
-  for (int k1 = 0; k1 < N; ++k1) x[k1] = y[k1];
-  bzk::fft<N, 1>(x);
-  const T wp = a.w[a.pass];
-  T* acc = a.acc + c * a.acc_stride + size_t(j2) * N + j3;
-  if (a.loss) {
-    const long row = a.idx ? long(a.idx[c]) : long(c);
-    const size_t fb = size_t(row) * N * N * N + size_t(j2) * N + j3;
-#pragma unroll
-    for (int j1 = 0; j1 < N; ++j1) {
-      const T fj = load_f<T>(a.f, a.f_fp32, fb + size_t(j1) * N * N);
-      acc[size_t(j1) * N * N] -= (wp * fj - x[j1].y) * x[j1].x;
-    }
-  } else if (a.first) {
-#pragma unroll
-    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] = wp * x[j1].x * x[j1].y;
-  } else {
-#pragma unroll
-    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N * N] += wp * x[j1].x * x[j1].y;
-  }
 }
 
 // ------------------------------------------------------------------ spectral resampling
@@ -1123,25 +1061,14 @@ template <typename T, int N>
 void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   const long threads = long(ncells) * N * N;
   const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+  constexpr int NG = N / (4 * plain_planes_per_wave<N>());
+  const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
   a.m1 = m1;
-  if constexpr (bz::plain_chunked(N, sizeof(T) == 4)) {
-    constexpr int NG = N / (4 * plain_planes_per_wave<N>());
-    const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
-    for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
-      a.pass = p0;
-      a.first = p0 == 0;
-      hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
-      hipLaunchKernelGGL((k_pBC<T, N>), grid_bc, block_bc, 0, s, a);
-    }
-    return;
-  }
-  for (int p = 0; p < m1; ++p) {
-    a.pass = p;
-    a.first = p == 0;
-    a.loss = p == m1 - 1;
-    hipLaunchKernelGGL((k_dirA<T, N>), grid, block, 0, s, a);
-    hipLaunchKernelGGL((k_dirB<T, N>), grid, block, 0, s, a);
-    hipLaunchKernelGGL((k_dirC<T, N>), grid, block, 0, s, a);
+  for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
+    a.pass = p0;
+    a.first = p0 == 0;
+    hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_pBC<T, N>), grid_bc, block_bc, 0, s, a);
   }
 }
 
@@ -1436,8 +1363,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   }
   if (st != BZ_OK) return st;
   if (timed) (void)hipEventRecord(pm->ev[2], s);
-  if (!fused_projection &&
-      !launch_project(p->n, p->transform == BZ_XF_PLAIN && plain_chunked(p->n, p->fp32), pa, ncells, s))
+  if (!fused_projection && !launch_project(p->n, p->transform == BZ_XF_PLAIN, pa, ncells, s))
     return fail(BZ_ERR_UNSUPPORTED, "projection: n=%d", p->n);
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);

@@ -460,7 +460,7 @@ void layout(bz_plan* p) {
   // chunked plain path: a chunk of plain_chunk(n) directions shares the stage-A output
   // (one volume per direction); fused: an FP32 copy of f in the collision
   // kernel's loss-pass order
-  p->ws.y_cell = fused ? align256(n3 * sizeof(float)) : align256(n3 * 2 * es * (plain_chunked(p->n, p->fp32) ? plain_chunk(p->n) : 1));
+  p->ws.y_cell = fused ? align256(n3 * sizeof(float)) : align256(n3 * 2 * es * plain_chunk(p->n));
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
   p->ws_fixed = kStatusBytes;  // the numeric status word of the plan's evaluations
