@@ -113,6 +113,21 @@ def test_n32_full_batch_sampled():
     assert drift <= 1e-12
 
 
+def test_n32_fp64_full_batch_sampled():
+    """The FP64 GPU path the FP32 speedup is measured against, in its benchmarked
+    launch (256 cells, N=32, M=32, chunked plain passes): sampled cells against
+    the oracle to 1e-12."""
+    label("n32 fp64 full batch")
+    f = gen.shock_batch(256, 32, 8.0, seed=2)
+    col = collider(32, 256, 0)
+    q = run(col, f, f_dtype=torch.float64)
+    assert np.isfinite(q).all()
+    sample = [1, 100, 254]
+    ref, loss = oracle_cells(f[sample], oracle_plan(32))
+    err = cell_errors(q[sample], ref, loss)
+    assert err.max() <= 1e-12, err
+
+
 @pytest.mark.parametrize("n,precision,tol", [(24, 1, 1e-5), (24, 0, 1e-12), (48, 1, 1e-5)])
 def test_radix3_sizes(n, precision, tol):
     label("radix3", n, precision)
