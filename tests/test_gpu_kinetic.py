@@ -119,6 +119,35 @@ def test_imex_euler_against_oracle(n, rule, m, prec, slices):
     col.close()
 
 
+def test_imex_benchmarked_batch_sampled():
+    """The benchmarked IMEX launch: 256 shock cells, N = 32, M = 32 spiral, FP32
+    fused collision with the IMEX epilogue, v1 f as the transport term, dt = eps
+    = 0.01; sampled cells against the oracle within the Q bound carried through
+    the update."""
+    import paper_2505_03360_amd as bz
+    print("case imex 256 cells", flush=True)
+    n, L, dt, eps, cells = 32, 8.0, 0.01, 0.01, 256
+    f = gen.shock_batch(cells, n, L, seed=2)
+    tr = f * gen.velocity_axis(n, L).reshape(1, n, 1, 1)
+    col = bz.Collider(n, cells, L=L, precision=bz.BZ_FP32, **lib_kwargs("spiral", 32))
+    out = col.imex_euler(torch.from_numpy(f).cuda(), torch.from_numpy(tr).cuda(), dt, eps=eps)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    assert np.isfinite(out).all()
+    sample = [0, 90, 255]
+    q_ref, loss_ref = oracle_cells(f[sample], oracle_plan(n, rule="spiral", m=32))
+    for i, c in enumerate(sample):
+        ref = kinetic.imex_combine(f[c], tr[c], q_ref[i], dt, eps, L)
+        rho1 = kinetic.conserved(f[c] - dt * tr[c], n, L)[0]
+        sens = dt / (eps + 2 * math.pi * rho1 * dt)
+        qn = max(np.linalg.norm(q_ref[i]), 0.05 * np.linalg.norm(loss_ref[i]))
+        err = np.linalg.norm(out[c] - ref)
+        bound = 1e-5 * sens * qn + 1e-13 * np.linalg.norm(ref)
+        print(f"  cell {c}: err {err:.3e} bound {bound:.3e}", flush=True)
+        assert err <= bound
+    col.close()
+
+
 def test_imex_equilibrium_and_conservation():
     # f^n Maxwellian, no transport: f^{n+1} = f^n + dt Q(M)/(eps + beta dt) stays Maxwellian;
     # with transport the invariants of f^{n+1} are those of f^n - dt tr
