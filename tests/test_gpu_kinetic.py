@@ -148,6 +148,33 @@ def test_imex_benchmarked_batch_sampled():
     col.close()
 
 
+def test_moments_and_esbgk_benchmarked_batch_sampled():
+    """The benchmarked launches of the moments and the ES-BGK operator (256 shock
+    cells, N = 32, beta = -1/2, mu0 = 1): every cell's moments and sampled
+    ES-BGK outputs against the oracle."""
+    import paper_2505_03360_amd as bz
+    print("case moments + esbgk 256 cells", flush=True)
+    n, L, cells, beta, mu0 = 32, 8.0, 256, -0.5, 1.0
+    f = gen.shock_batch(cells, n, L, seed=2)
+    ft = torch.from_numpy(f).cuda()
+    got = bz.cell_moments(ft, L)
+    q = bz.esbgk_collide(ft, L, beta, mu0)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    q = q.cpu().numpy()
+    for c in range(0, cells, 17):
+        rho, u, T = kinetic.moments(f[c], n, L)
+        assert abs(got["rho"][c] - rho) <= 1e-13 * rho
+        assert abs(got["T"][c] - T) <= 1e-12 * T
+        assert abs(got["l1"][c] - kinetic.l1_distance(f[c], n, L)) <= 1e-12 * rho
+    for c in (0, 128, 255):
+        ref = kinetic.esbgk_collide(f[c], n, L, beta, mu0)
+        rho, u, th = kinetic.stress(f[c], n, L)
+        nu = kinetic.esbgk_frequency(rho, np.trace(th) / 3, beta, mu0)
+        floor = max(np.linalg.norm(ref), 0.05 * nu * np.linalg.norm(f[c]))
+        assert np.linalg.norm(q[c] - ref) / floor <= 1e-12
+
+
 def test_imex_equilibrium_and_conservation():
     # f^n Maxwellian, no transport: f^{n+1} = f^n + dt Q(M)/(eps + beta dt) stays Maxwellian;
     # with transport the invariants of f^{n+1} are those of f^n - dt tr
