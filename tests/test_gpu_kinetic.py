@@ -272,6 +272,31 @@ def test_pr222_against_oracle(n, rule, m, prec):
     col.close()
 
 
+def test_pr222_benchmarked_batch_sampled():
+    """The benchmarked PR(2,2,2) step (256 shock cells, N = 32, M = 32 spiral,
+    FP32, zero transport, dt = eps = 0.01): sampled cells against the oracle."""
+    import paper_2505_03360_amd as bz
+    print("case pr222 256 cells", flush=True)
+    n, L, dt, eps, cells = 32, 8.0, 0.01, 0.01, 256
+    f = gen.shock_batch(cells, n, L, seed=2)
+    plan = oracle_plan(n, rule="spiral", m=32)
+    col = bz.Collider(n, cells, L=L, precision=bz.BZ_FP32, **lib_kwargs("spiral", 32))
+    ft = torch.from_numpy(f).cuda()
+    zero = torch.zeros_like(ft)
+    out = col.pr222_step(ft, lambda z: zero, dt, eps=eps).cpu().numpy()
+    assert np.isfinite(out).all()
+    sample = [5, 250]
+    q_ref, loss_ref = oracle_cells(f[sample], plan)
+    for i, c in enumerate(sample):
+        ref = kinetic.pr222_step(f[c], lambda z: np.zeros_like(z), dt, eps, plan)
+        qn = max(np.linalg.norm(q_ref[i]), 0.05 * np.linalg.norm(loss_ref[i]))
+        err = np.linalg.norm(out[c] - ref)
+        bound = 4 * 1e-5 * (dt / eps) * qn + 1e-13 * np.linalg.norm(ref)
+        print(f"  cell {c}: err {err:.3e} bound {bound:.3e}", flush=True)
+        assert err <= bound
+    col.close()
+
+
 @pytest.mark.parametrize("n", [16, 32])
 def test_esbgk_pr222_against_oracle(n):
     import paper_2505_03360_amd as bz
