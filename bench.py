@@ -125,12 +125,15 @@ def cpu_baseline_fft(f, budget_s: float = 10.0, n: int = N, m: int = M, gamma: f
                       f"{cores} threads over cells, {dt:.1f} s"}
 
 
-def serving_run(seconds: float, seed: int = 5):
-    """Serving workload: 4 client threads, each keeping two requests in flight;
-    a request has N drawn from {16, 24, 32, 48}, M = 32, cells ~ Poisson(512)
-    clipped to [16, 4096], FP32 input, FP32 evaluation + FP64 projection;
-    24 GiB arena (a 4096-cell request at N = 48 needs 20 GB), so that admission
-    by memory binds.  Latency = done - submit."""
+def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
+    """Serving workload: 4 client threads; a request has N drawn from {16, 24,
+    32, 48}, M = 32, cells ~ Poisson(512) clipped to [16, 4096], FP32 input,
+    FP32 evaluation + FP64 projection; 24 GiB arena (a 4096-cell request at
+    N = 48 needs 20 GB), so that admission by memory binds.  Latency = done -
+    submit, from the server's own clock.  First a closed loop (each client keeps
+    two requests in flight for `seconds`) measures the capacity; then an open
+    loop offers Poisson arrivals at 80 % of that capacity, `open_requests` per
+    client, whatever is still in flight."""
     import threading
 
     import numpy as np
@@ -200,14 +203,77 @@ def serving_run(seconds: float, seed: int = 5):
     for t in th:
         t.join()
     dt = time.perf_counter() - t0
+    lat = np.array(lat)
+    rec = {"clients": 4, "sizes": list(sizes), "m": M, "requests": int(lat.size), "failed": failed[0],
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "cells_per_s": cells[0] / dt, "seconds": dt,
+           "workload": "4 clients x 2 in flight, N in {16,24,32,48}, M=32, Poisson(512) cells in [16,4096], "
+                       "FP32 + FP64 projection, 24 GiB arena"}
+    if open_requests > 0:
+        # mean cells per request of the clipped Poisson(512) draw
+        mean_cells = float(np.clip(np.random.default_rng(seed).poisson(512, 200000), 16, 4096).mean())
+        rate = 0.8 * rec["cells_per_s"] / mean_cells  # requests per second over the 4 clients
+        olat, ocells, ofailed, orejected = [], [0], [0], [0]
+
+        def open_client(cid):
+            rng = np.random.default_rng(seed * 1000 + cid)
+            inflight = []
+
+            def reap(block):
+                keep = []
+                for t, kk, q in inflight:
+                    done, r = srv.poll(t)
+                    if not done and block:
+                        r = wait(t)
+                        done = True
+                    if not done:
+                        keep.append((t, kk, q))
+                        continue
+                    with lock:
+                        if r.state == bz.BZ_REQ_DONE:
+                            olat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+                            ocells[0] += kk
+                        else:
+                            ofailed[0] += 1
+                inflight[:] = keep
+            next_t = time.perf_counter() + rng.exponential(4.0 / rate)
+            issued = 0
+            while issued < open_requests:
+                reap(False)
+                now = time.perf_counter()
+                if now < next_t:
+                    time.sleep(min(next_t - now, 0.0005))
+                    continue
+                n = int(rng.choice(sizes))
+                k = int(np.clip(rng.poisson(512), 16, 4096))
+                q = torch.empty((k, n, n, n), dtype=torch.float64, device="cuda")
+                t = srv.submit(pool[n][:k], q, plans[n], client_id=cid)
+                if t is None:
+                    with lock:
+                        orejected[0] += 1
+                else:
+                    inflight.append((t, k, q))
+                issued += 1
+                next_t += rng.exponential(4.0 / rate)
+            reap(True)
+        t0 = time.perf_counter()
+        th = [threading.Thread(target=open_client, args=(c,)) for c in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        odt = time.perf_counter() - t0
+        olat = np.array(olat)
+        rec["open_loop"] = {
+            "offered_requests_per_s": rate, "offered_cells_per_s": rate * mean_cells,
+            "requests": int(olat.size), "failed": ofailed[0], "rejected": orejected[0],
+            "p50_ms": float(np.percentile(olat, 50)), "p99_ms": float(np.percentile(olat, 99)),
+            "cells_per_s": ocells[0] / odt, "seconds": odt,
+            "workload": f"Poisson arrivals at 80 % of the closed-loop capacity, {open_requests} requests per client"}
     st = srv.stats()
     srv.close()
-    lat = np.array(lat)
-    return {"clients": 4, "sizes": list(sizes), "m": M, "requests": int(lat.size), "failed": failed[0],
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "cells_per_s": cells[0] / dt, "seconds": dt, "arena_peak_gib": st.arena_peak / 2 ** 30,
-            "workload": "4 clients x 2 in flight, N in {16,24,32,48}, M=32, Poisson(512) cells in [16,4096], "
-                        "FP32 + FP64 projection, 24 GiB arena"}
+    rec["arena_peak_gib"] = st.arena_peak / 2 ** 30
+    return rec
 
 
 def peak_probe(blocks: int = 256 * 8, iters: int = 2048, reps: int = 5):
@@ -520,6 +586,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0, help="serving run length (0 = skip)")
+    ap.add_argument("--serve-open-requests", type=int, default=300,
+                    help="open-loop serving requests per client at 80%% of capacity (0 = skip)")
     ap.add_argument("--sweep", action="store_true", help="run the precision sweep instead (one JSON line per case)")
     ap.add_argument("--sweep-n", type=int, nargs="*", default=[32, 48])
     ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
@@ -632,8 +700,9 @@ def main():
     if args.serve_seconds > 0:
         del out64, col64
         torch.cuda.empty_cache()
-        rec["serving"] = serving_run(args.serve_seconds)
-        rec["p99_latency_ms"] = rec["serving"]["p99_ms"]
+        rec["serving"] = serving_run(args.serve_seconds, open_requests=args.serve_open_requests)
+        ol = rec["serving"].get("open_loop")
+        rec["p99_latency_ms"] = ol["p99_ms"] if ol else rec["serving"]["p99_ms"]
     if not args.no_cpu:
         plan = oracle_plan()
         rec["cpu_baseline"] = cpu_baseline(f_np, args.cpu_budget, plan=plan)
