@@ -286,34 +286,40 @@ __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
   }
 }
 
+// Planes of fixed j3 per k_pBC workgroup, one thread per pencil: the largest
+// divisor of N whose planes fit 256 threads (N = 16: 16 planes, 24: 8 on 192
+// threads, 32: 8, 48: 4 on 192 threads), so every lane of the workgroup is busy.
 template <int N>
-constexpr int plain_planes_per_wave() { return 64 / N; }
+constexpr int plain_planes_per_group() {
+  int pw = 1;
+  for (int d = 1; d * N <= 256; ++d)
+    if (N % d == 0) pw = d;
+  return pw;
+}
 
 template <typename T, int N>
 __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
-  constexpr int PL = plain_planes_per_wave<N>();  // planes per wave
-  constexpr int PW = 4 * PL;                      // planes per workgroup
-  constexpr int NG = N / PW;                      // workgroups per cell
-  static_assert(N % PW == 0, "planes must tile the cell");
+  constexpr int PW = plain_planes_per_group<N>();  // planes per workgroup
+  constexpr int NG = N / PW;                       // workgroups per cell
+  static_assert(N % PW == 0 && PW * N <= 256, "planes must tile the cell");
   __shared__ cx<T> tr[PW][N][N + 1];  // [plane][j2][k1], odd pitch
   const int c = blockIdx.x / NG, grp = blockIdx.x % NG;
   if (c >= live_count(a.ncells, a.ncells_dev)) return;
-  const int t = threadIdx.x, wv = t / 64, lane = t % 64;
-  const bool act = lane < PL * N;
-  const int pl = wv * PL + (act ? lane / N : 0);
-  const int k = lane % N;  // stage B: k1; stage C: j2
+  const int t = threadIdx.x;
+  const int pl = t / N;  // the block holds exactly PW * N threads
+  const int k = t % N;   // stage B: k1; stage C: j2
   const int j3 = grp * PW + pl;
   T* acc = a.acc + c * a.acc_stride + size_t(j3) * N * N;  // [j1][j2] of plane j3
   T accr[N];
 #pragma unroll
-  for (int j1 = 0; j1 < N; ++j1) accr[j1] = (act && !a.first) ? acc[size_t(j1) * N + k] : T(0);
+  for (int j1 = 0; j1 < N; ++j1) accr[j1] = !a.first ? acc[size_t(j1) * N + k] : T(0);
   const long row = a.idx ? long(a.idx[c]) : long(c);
 #pragma unroll 1
   for (int d = 0; d < plain_chunk(N); ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const T wp = a.w[p];
-    if (act) {
+    {
       const gptr<cx<T>> y = opaque_global(a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(j3) * N * N + k);
       cx<T> x[N];
 #pragma unroll
@@ -323,7 +329,7 @@ __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
       for (int j2 = 0; j2 < N; ++j2) tr[pl][j2][k] = x[j2];
     }
     __syncthreads();
-    if (act) {
+    {
       cx<T> x[N];
 #pragma unroll
       for (int r = 0; r < N; ++r) {
@@ -350,9 +356,8 @@ __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
     }
     __syncthreads();  // tr is rewritten by the next direction
   }
-  if (act)
 #pragma unroll
-    for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N + k] = accr[j1];
+  for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N + k] = accr[j1];
 }
 
 // ------------------------------------------------------------------ fused FP32
@@ -1061,8 +1066,8 @@ template <typename T, int N>
 void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   const long threads = long(ncells) * N * N;
   const dim3 grid(unsigned((threads + 255) / 256)), block(256);
-  constexpr int NG = N / (4 * plain_planes_per_wave<N>());
-  const dim3 grid_bc(unsigned(long(ncells) * NG)), block_bc(256);
+  constexpr int PW = plain_planes_per_group<N>();
+  const dim3 grid_bc(unsigned(long(ncells) * (N / PW))), block_bc(unsigned(PW * N));
   a.m1 = m1;
   for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
     a.pass = p0;
