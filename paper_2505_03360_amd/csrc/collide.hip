@@ -80,6 +80,7 @@ struct PlainArgs {
   const T* w;         // [pass]
   int pass;
   int first;  // the chunk starting at pass 0 (initialises the accumulator)
+  int chunk;  // directions per chunk (stage-A volumes per cell in y)
   int m1;     // passes (directions + the loss pass)
 };
 
@@ -252,10 +253,9 @@ __global__ __launch_bounds__(256) void k_rsC(PlainArgs<T> a) {
 //          k1, products accumulated in registers over the chunk, accumulator
 //          kept plane-major acc[cell][j3][j1][j2].
 // Per cell and direction this moves fhat/K + y twice + acc twice/K (K the
-// chunk, plain_chunk(N)) instead of fhat + y four times + acc twice.  k_pA
+// chunk, the plan's pchunk) instead of fhat + y four times + acc twice.  k_pA
 // streams fhat in and y out past the L2 (non-temporal), which keeps the
 // chunk's multiplier tables, shared by every cell, resident there.
-using bz::plain_chunk;
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_pA(PlainArgs<T> a) {
   cx<T> F[N];
 #pragma unroll
   for (int k3 = 0; k3 < N; ++k3) F[k3] = nt_load(fh + size_t(k3) * N);
-  for (int d = 0; d < plain_chunk(N); ++d) {
+  for (int d = 0; d < a.chunk; ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const cx<T>* mu = a.mult + size_t(p) * N * N * N + off;
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
   for (int j1 = 0; j1 < N; ++j1) accr[j1] = !a.first ? acc[size_t(j1) * N + k] : T(0);
   const long row = a.idx ? long(a.idx[c]) : long(c);
 #pragma unroll 1
-  for (int d = 0; d < plain_chunk(N); ++d) {
+  for (int d = 0; d < a.chunk; ++d) {
     const int p = a.pass + d;
     if (p >= a.m1) break;
     const T wp = a.w[p];
@@ -1069,7 +1069,7 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
   constexpr int PW = plain_planes_per_group<N>();
   const dim3 grid_bc(unsigned(long(ncells) * (N / PW))), block_bc(unsigned(PW * N));
   a.m1 = m1;
-  for (int p0 = 0; p0 < m1; p0 += plain_chunk(N)) {
+  for (int p0 = 0; p0 < m1; p0 += a.chunk) {
     a.pass = p0;
     a.first = p0 == 0;
     hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
@@ -1080,6 +1080,8 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
 template <typename T>
 bz_status run_plain(const bz_plan* p, const PlainArgs<T>& a, int ncells, hipStream_t s, bool fwd_only,
                     bool timed) {
+  if (!fwd_only && (a.chunk < 1 || a.chunk > bz::kPlainChunkMax))
+    return bz::fail(BZ_ERR_STATE, "plain path: %d directions per chunk", a.chunk);
   switch (p->n) {
     case 16:
       launch_plain_forward<T, 16>(a, ncells, s);
@@ -1296,6 +1298,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
     a.acc = reinterpret_cast<float*>(ws + lay.acc_off);
     a.fh_stride = lay.fh_cell / sizeof(cx<float>);
     a.y_stride = lay.y_cell / sizeof(cx<float>);
+    a.chunk = p->pchunk;
     a.acc_stride = lay.acc_cell / sizeof(float);
     a.mult = static_cast<const cx<float>*>(b.tables);
     a.w = reinterpret_cast<const float*>(static_cast<const char*>(b.tables) + p->table_w_off);
@@ -1361,6 +1364,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
     a.acc = reinterpret_cast<double*>(ws + lay.acc_off);
     a.fh_stride = lay.fh_cell / sizeof(cx<double>);
     a.y_stride = lay.y_cell / sizeof(cx<double>);
+    a.chunk = p->pchunk;
     a.acc_stride = lay.acc_cell / sizeof(double);
     a.mult = static_cast<const cx<double>*>(b.tables);
     a.w = reinterpret_cast<const double*>(static_cast<const char*>(b.tables) + p->table_w_off);

@@ -457,10 +457,11 @@ void layout(bz_plan* p) {
   const bool fused = p->transform == BZ_XF_FUSED;
   const int acc_chunks = fused ? ((p->chunks == 1 && p->project) ? 0 : p->chunks) : 1;
   p->ws.fh_cell = align256(n3 * 2 * es);
-  // chunked plain path: a chunk of plain_chunk(n) directions shares the stage-A output
+  // chunked plain path: a chunk of pchunk directions shares the stage-A output
   // (one volume per direction); fused: an FP32 copy of f in the collision
   // kernel's loss-pass order
-  p->ws.y_cell = fused ? align256(n3 * sizeof(float)) : align256(n3 * 2 * es * plain_chunk(p->n));
+  p->pchunk = fused ? 0 : plain_chunk(p->n, p->fp32 != 0, p->d.max_cells);
+  p->ws.y_cell = fused ? align256(n3 * sizeof(float)) : align256(n3 * 2 * es * p->pchunk);
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
   p->ws_fixed = kStatusBytes;  // the numeric status word of the plan's evaluations

@@ -93,7 +93,7 @@ struct Arena {
 struct PlanKey {
   bz_plan_desc d{};
   std::vector<double> dirs, weights;
-  int chunk_class = 0;  // default direction chunks for the request size (plans differ by it)
+  int chunk_class = 0;  // chunk choices that follow from the request size (plans differ by them)
   bool operator==(const PlanKey& o) const {
     return chunk_class == o.chunk_class && d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
            d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
@@ -107,9 +107,14 @@ struct PlanKey {
 PlanKey make_key(const bz_plan_desc& d, int ncells) {
   PlanKey k;
   k.d = d;
-  // a plan left to pick its own chunks picks them from its capacity: requests
-  // of different size classes get (and cache) different plans
-  if (d.chunks == 0 && d.dim != 2) k.chunk_class = bz::fused_default_chunks(d.n, std::max(1, ncells));
+  // a plan picks its direction chunks (fused path, when left open) and its
+  // plain-path chunk from its capacity: requests of different size classes get
+  // (and cache) different plans
+  if (d.dim != 2) {
+    const int nc = std::max(1, ncells);
+    if (d.chunks == 0) k.chunk_class = bz::fused_default_chunks(d.n, nc);
+    k.chunk_class = k.chunk_class * 16 + bz::plain_chunk(d.n, d.precision == BZ_FP32, nc);
+  }
   k.d.max_cells = 0;
   k.d.dirs = nullptr;
   k.d.weights = nullptr;
