@@ -95,7 +95,10 @@ typedef struct {
   int32_t transform;     /* BZ_XF_* */
   int32_t project;       /* 1: FP64 conservative projection, FP64 output;
                             0: raw Q in the plan precision */
-  int32_t max_cells;     /* largest batch the bound workspace must hold */
+  int32_t max_cells;     /* largest batch the bound workspace must hold; also sets
+                            the plain path's directions per chunk at n = 48
+                            (FP32: 8 up to 1024 cells, else 4; results do not
+                            depend on it) */
   int32_t chunks;        /* fused path: direction chunks per cell, each a workgroup;
                             0 = from max_cells (n = 32: 4 up to 64 cells, 2 up to
                             128, else 1; n = 16: 4 up to 256, 2 up to 512), unless
