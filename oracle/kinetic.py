@@ -263,3 +263,32 @@ def esbgk_pr222_step(y: np.ndarray, transport, dt: float, eps: float, L: float, 
     for i in range(2):
         out = out + dt * PR_W_EXP[i] * qs[i] + dt * PR_W_IMP[i] * gs[i] / eps
     return out
+
+
+def realizability_matrix(f: np.ndarray, n: int, L: float) -> np.ndarray:
+    """Moment realizability matrix of the appendix (Moment realizability
+    matrix): with V = (v - u)/sqrt(T) and the reduced invariants
+    m = (1, V, (2/5)^(1/2) (|V|^2/2 - 5/2)),  M = (1/rho) int m (x) m f dv
+    (5 x 5; u and T from moments(f))."""
+    rho, u, T = moments(f, n, L)
+    v1, v2, v3, dv3 = _grid(n, L)
+    s = 1.0 / math.sqrt(T)
+    V = [(v1 - u[0]) * s, (v2 - u[1]) * s, (v3 - u[2]) * s]
+    m = [np.ones_like(v1)] + V + [math.sqrt(2.0 / 5.0) * ((V[0] ** 2 + V[1] ** 2 + V[2] ** 2) / 2.0 - 2.5)]
+    M = np.empty((5, 5))
+    for i in range(5):
+        for j in range(5):
+            M[i, j] = (m[i] * m[j] * f).sum() * dv3 / rho
+    return M
+
+
+def reduced_realizability(M: np.ndarray):
+    """Split M into Abar (M[1:4,1:4] - I), Bbar (M[1:4,4] / (2/5)^(1/2)) and
+    Cbar (M[4,4]), and return (Cbar, V) with the Schur-complement form
+    V = I + Abar - (2/(5 Cbar)) / (1 - 2/(5 Cbar)) Bbar (x) Bbar
+    (valid for Cbar > 2/5; Cbar = 1 gives I + Abar - (2/3) Bbar (x) Bbar)."""
+    A = M[1:4, 1:4] - np.eye(3)
+    B = M[1:4, 4] / math.sqrt(2.0 / 5.0)
+    C = M[4, 4]
+    k = 2.0 / (5.0 * C)
+    return C, np.eye(3) + A - (k / (1.0 - k)) * np.outer(B, B)

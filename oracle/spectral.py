@@ -330,3 +330,33 @@ def rel_err(q_test: np.ndarray, q_ref: np.ndarray, loss_ref: np.ndarray | None =
     if loss_ref is not None:
         den = max(den, 0.05 * np.linalg.norm(loss_ref))
     return float(np.linalg.norm(q_test - q_ref) / den)
+
+
+def bhat_pair(lv, mv, R: float, gamma: float, dirs, weights) -> np.ndarray:
+    """The direction rule's approximation of the spectral kernel Bhat(l, m):
+    sum_p w_p phi_R(l . e_p) psi_R(|m - (m . e_p) e_p|) for wave vectors
+    lv, mv [K, 3] (the sum over directions that replaces the half-sphere
+    integral in Sec. 4.4.1, beta_F = sum_p alpha_p(l) alpha'_p(m))."""
+    lv = np.atleast_2d(np.asarray(lv, dtype=np.float64))
+    mv = np.atleast_2d(np.asarray(mv, dtype=np.float64))
+    e = np.asarray(dirs, dtype=np.float64)
+    s = lv @ e.T                                   # [K, P]
+    me = mv @ e.T
+    perp2 = (mv * mv).sum(axis=1)[:, None] - me * me
+    r = np.sqrt(np.maximum(perp2, 0.0))
+    return (phi(s, R, gamma) * psi(r, R)) @ np.asarray(weights, dtype=np.float64)
+
+
+def hemisphere_gauss_rule(n_theta: int, n_phi: int):
+    """Product rule on the half sphere z >= 0: Gauss-Legendre nodes in
+    z = cos(theta) on [0, 1] times n_phi equally spaced azimuths; weights sum
+    to 2 pi.  Used as the converged reference for Bhat(l, m)."""
+    x, w = np.polynomial.legendre.leggauss(n_theta)
+    z = 0.5 * (x + 1.0)
+    wz = 0.5 * w
+    ph = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    Z, PH = np.meshgrid(z, ph, indexing="ij")
+    S = np.sqrt(1.0 - Z * Z)
+    dirs = np.stack([(S * np.cos(PH)).ravel(), (S * np.sin(PH)).ravel(), Z.ravel()], axis=1)
+    wts = (wz[:, None] * np.full(n_phi, 2.0 * math.pi / n_phi)[None, :]).ravel()
+    return dirs, wts

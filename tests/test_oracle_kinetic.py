@@ -331,3 +331,65 @@ def test_esbgk_pr222_order_and_conservation():
         errs.append(np.linalg.norm(y - ref))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.5 <= r1 <= 5.0 and 3.5 <= r2 <= 5.0, errs
+
+
+# ---------------------------------------------------------------- P13 (diagnostic)
+def _thirteen_moment(n, L, rho, u, T, q, tau):
+    """f = M (1 + phi) with the heat-flux and stress perturbation printed in
+    the appendix (Moment realizability matrix)."""
+    M = kinetic.maxwellian(rho, u, T, n, L)
+    v = spectral.velocity_nodes(n, L)
+    V = np.meshgrid(v, v, v, indexing="ij")
+    c = [V[i] - u[i] for i in range(3)]
+    c2 = c[0] ** 2 + c[1] ** 2 + c[2] ** 2
+    cq = c[0] * q[0] + c[1] * q[1] + c[2] * q[2]
+    ctc = sum(c[i] * tau[i, j] * c[j] for i in range(3) for j in range(3))
+    phi = cq / (rho * T * T) * (c2 / (5 * T) - 1) + ctc / (2 * rho * T * T)
+    return M * (1 + phi)
+
+
+def test_p13_maxwellian_matrix_and_thirteen_moment_cbar():
+    """At equilibrium M has the printed block form with Abar = Bbar = 0 and
+    Cbar = 1; for f = M(1 + phi) (heat flux q, traceless stress tau) Cbar stays
+    1 and the reduced matrix is I + Abar - (2/3) Bbar Bbar^T."""
+    n, L = 32, 8.0
+    f = kinetic.maxwellian(1.3, [0.2, -0.1, 0.3], 1.1, n, L)
+    Mx = kinetic.realizability_matrix(f, n, L)
+    ref = np.eye(5)
+    ref[0, 4] = ref[4, 0] = -math.sqrt(2 / 5)
+    assert np.abs(Mx - ref).max() <= 1e-9  # grid quadrature of fourth moments
+    tau = np.array([[0.05, 0.02, 0.0], [0.02, -0.03, 0.01], [0.0, 0.01, -0.02]])
+    f = _thirteen_moment(n, L, 1.0, np.zeros(3), 1.0, np.array([0.04, -0.02, 0.03]), tau)
+    Mx = kinetic.realizability_matrix(f, n, L)
+    C, V = kinetic.reduced_realizability(Mx)
+    assert abs(C - 1.0) <= 5e-3  # Cbar = 1 to first order in (q, tau)
+    A = Mx[1:4, 1:4] - np.eye(3)
+    B = Mx[1:4, 4] / math.sqrt(2 / 5)
+    V1 = np.eye(3) + A - (2 / 3) * np.outer(B, B)
+    assert np.abs(V - V1).max() <= 5e-3
+    assert np.linalg.eigvalsh(V).min() > 0 and np.linalg.eigvalsh(Mx).min() > 0
+
+
+def test_p13_psd_equivalence():
+    """M is positive semi-definite iff V is, whenever Cbar > 2/5 (Schur
+    complement, then the congruence W = Q^T X Q = diag(Cbar, V)); checked on
+    perturbations that grow until f takes negative values."""
+    n, L = 24, 8.0
+    rng = np.random.default_rng(13)
+    seen = {True: 0, False: 0}
+    for amp in (0.05, 0.3, 0.8, 1.5, 3.0, 6.0):
+        for _ in range(6):
+            q = amp * rng.normal(size=3)
+            t = amp * rng.normal(size=(3, 3))
+            t = 0.5 * (t + t.T)
+            t -= np.trace(t) / 3 * np.eye(3)
+            f = _thirteen_moment(n, L, 1.0, np.zeros(3), 1.0, q, t)
+            Mx = kinetic.realizability_matrix(f, n, L)
+            C, V = kinetic.reduced_realizability(Mx)
+            if not C > 0.4:
+                continue
+            psd_m = np.linalg.eigvalsh(Mx).min() >= -1e-12
+            psd_v = np.linalg.eigvalsh(V).min() >= -1e-12
+            assert psd_m == psd_v, (amp, np.linalg.eigvalsh(Mx), np.linalg.eigvalsh(V))
+            seen[psd_m] += 1
+    assert seen[True] > 0 and seen[False] > 0, seen

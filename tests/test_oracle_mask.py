@@ -143,3 +143,81 @@ def test_compaction_ascending_and_margin():
     assert np.all(np.diff(idx) > 0)
     assert len(idx) == int((out == 2).sum())
     assert om.margin_cells(d, lam) == 0
+
+
+# ---------------------------------------------------------------- border (ghost cells)
+# At the border the stencil reads the nearest cell in place of the missing
+# neighbour (the ghost cells of Sec. 5 copy it).  For fields linear or
+# quadratic in x or y this gives closed forms that differ from the interior:
+#   first derivative of a x at ix = 0 and nx-1:  a dx / (2 dx) = a / 2;
+#   Laplacian of b x^2 (x = ix dx) over dx dy:
+#     ix = 0:      (q1 - q0) / (dx dy)             =  b dx / dy,
+#     ix = nx-1:   (q[nx-2] - q[nx-1]) / (dx dy)   = -b (2 nx - 3) dx / dy,
+#     interior:    2 b dx / dy.
+def test_border_first_derivative_of_linear_temperature():
+    """T = 1 + a x, rho = 1, u = 0: lambda_a = lambda_c = 1,
+    lambda_b = 1 - xi2 Tx^2, lambda_B = eps^2 Tx^2 / T with Tx = a/2 on the
+    first and last columns and a inside; likewise along y."""
+    nx, ny = 9, 7
+    dx, dy = 0.1, 0.2
+    a, eps = 0.3, 1e-2
+    for axis in ("x", "y"):
+        X = np.arange(nx)[None, :] * dx + 0 * np.arange(ny)[:, None]
+        Y = np.arange(ny)[:, None] * dy + 0 * np.arange(nx)[None, :]
+        T = 1.0 + a * (X if axis == "x" else Y)
+        one = np.ones((ny, nx))
+        d = om.MaskDesc(nx=nx, ny=ny, dx=dx, dy=dy)
+        la, lb, lc, lB = om.indicators(d, one, 0 * one, 0 * one, T, eps * one)
+        idx = np.arange(nx if axis == "x" else ny)
+        border = (idx == 0) | (idx == idx[-1])
+        g = np.where(border, a / 2, a)
+        G = np.broadcast_to(g[None, :] if axis == "x" else g[:, None], (ny, nx))
+        kap = d.kappa0 * np.sqrt(T)
+        xi2 = eps * eps * 2 * kap * kap / (3 * T ** 3)
+        assert np.allclose(lB, eps * eps * G * G / T, rtol=1e-13, atol=0)
+        assert np.allclose(lb, 1 - xi2 * G * G, rtol=0, atol=1e-15)
+        assert np.all(la == 1.0) and np.all(lc == 1.0)
+
+
+def test_border_laplacian_of_quadratic_density():
+    """rho = 1 + b x^2, T = 1, u = 0: lambda_B = eps^2 sqrt(2) |Lap rho| / rho
+    with the one-sided border Laplacians above (and the same along y)."""
+    nx, ny = 8, 6
+    dx, dy = 0.125, 0.25
+    b, eps = 0.7, 1e-2
+    for axis in ("x", "y"):
+        nn, h, hh = (nx, dx, dy) if axis == "x" else (ny, dy, dx)
+        i = np.arange(nn)
+        lap = np.full(nn, 2 * b * h / hh)
+        lap[0] = b * h / hh
+        lap[-1] = -b * (2 * nn - 3) * h / hh
+        r1 = 1.0 + b * (i * h) ** 2
+        if axis == "x":
+            rho = np.broadcast_to(r1[None, :], (ny, nx)).copy()
+            LAP = np.broadcast_to(lap[None, :], (ny, nx))
+        else:
+            rho = np.broadcast_to(r1[:, None], (ny, nx)).copy()
+            LAP = np.broadcast_to(lap[:, None], (ny, nx))
+        one = np.ones((ny, nx))
+        d = om.MaskDesc(nx=nx, ny=ny, dx=dx, dy=dy)
+        lB = om.indicators(d, rho, 0 * one, 0 * one, one, eps * one)[3]
+        assert np.allclose(lB, eps * eps * math.sqrt(2) * np.abs(LAP) / rho, rtol=1e-13, atol=0)
+
+
+def test_border_shear_rows():
+    """ux = g y: the first and last rows see d ux/dy = g/2, so
+    lambda_{a,b} = 1 -+ xi1 g/2 and lambda_B = eps^2 (g/2)^2 there, plus the
+    one-sided Laplacian of ux: (q1 - q0)/(dx dy) = g dy/(dx dy) = g/dx on the
+    first row and -g/dx on the last (scalar mode: Lap u = Lap ux)."""
+    nx, ny = 5, 8
+    dx = dy = 0.125
+    g, eps = 0.5, 1e-2
+    Y = np.repeat((np.arange(ny) * dy)[:, None], nx, axis=1)
+    one = np.ones((ny, nx))
+    d = om.MaskDesc(nx=nx, ny=ny, dx=dx, dy=dy)
+    la, lb, lc, lB = om.indicators(d, one, g * Y, 0 * one, one, eps * one)
+    for row in (0, ny - 1):
+        assert np.allclose(la[row], 1 + eps * g / 2, rtol=0, atol=1e-15)
+        assert np.allclose(lb[row], 1 - eps * g / 2, rtol=0, atol=1e-15)
+        lap = g / dx
+        assert np.allclose(lB[row], eps * eps * ((g / 2) ** 2 + math.sqrt(2) * lap), rtol=1e-13, atol=0)
