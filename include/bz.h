@@ -56,8 +56,16 @@ enum {
   BZ_DIRS_ICOSA6 = 1,   /* six icosahedral axes, weight pi/3 (m must be 6) */
   BZ_DIRS_PRODUCT = 2,  /* theta_p=(p+1/2)pi/a1, phi_q=q pi/a2, weights ~ sin(theta) */
   BZ_DIRS_SPIRAL = 3,   /* equal-weight golden spiral, z_p=(p+1/2)/m */
-  BZ_DIRS_CIRCLE = 4    /* two velocity dimensions: theta_p = pi p/m, p = 1..m,
+  BZ_DIRS_CIRCLE = 4,   /* two velocity dimensions: theta_p = pi p/m, p = 1..m,
                            weight pi/m each (the only rule of dim = 2 plans) */
+  BZ_DIRS_DESIGN = 5    /* equal-weight antipodal spherical design, 2 <= m <= 256:
+                           the golden spiral moved by damped minimum-norm
+                           Gauss-Newton steps until sum_p Y_lm(e_p) = 0 for every
+                           real harmonic of even degree 2 <= l <= L, L the largest
+                           even degree with L (L + 3) / 2 <= 2m - 3 equations
+                           (lowered by 2 while the iteration stalls); the rule then
+                           integrates polynomials of degree <= t = L + 1 exactly
+                           (bz_plan_rule_degree; m = 32: t = 9, m = 64: t = 15) */
 };
 
 /* evaluation strategy */
@@ -184,6 +192,14 @@ bz_status bz_plan_strategy(const bz_plan* plan, int32_t* transform, int32_t* chu
 /* Host copies of the plan's direction rule: dirs [m][3], weights [m]
    (dim = 2: (cos theta_p, sin theta_p, 0) and pi/m). */
 bz_status bz_plan_get_rule(const bz_plan* plan, double* dirs, double* weights);
+
+/* Antipodal spherical-design degree t of the plan's direction rule: the
+   largest odd t such that the rule, extended to the whole sphere by e -> -e,
+   integrates every polynomial of degree <= t exactly (checked through
+   sum_{p,q} w_p w_q P_l(e_p . e_q) <= 1e-12 (sum w)^2 for every even l <= t - 1,
+   up to l = 80).  ICOSA6 gives 5; the spiral and product rules give 1;
+   BZ_ERR_UNSUPPORTED for dim = 2 plans. */
+bz_status bz_plan_rule_degree(const bz_plan* plan, int32_t* t);
 
 /* Host copy of the FP64 multipliers of pass p (0 <= p <= m; pass m is the
    loss pass (Bhat_M, 1)) as [k2][k3][k1][2] = (alpha_p, alpha'_p)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbz.so")
 BZ_OK, BZ_AGAIN = 0, 1
 BZ_ERR_ARG, BZ_ERR_UNSUPPORTED, BZ_ERR_DEVICE, BZ_ERR_NOMEM, BZ_ERR_STATE, BZ_ERR_NUMERIC = -1, -2, -3, -4, -5, -6
 BZ_FP64, BZ_FP32 = 0, 1
-BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL, BZ_DIRS_CIRCLE = 0, 1, 2, 3, 4
+BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL, BZ_DIRS_CIRCLE, BZ_DIRS_DESIGN = 0, 1, 2, 3, 4, 5
 BZ_XF_AUTO, BZ_XF_FUSED, BZ_XF_PLAIN = 0, 1, 2
 BZ_SCATTER = 1
 BZ_CELL_SOLID, BZ_CELL_FORCE_BOLTZMANN = 1, 2
@@ -135,6 +135,7 @@ SIGNATURES = [
     ("bz_plan_strategy", _I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("bz_plan_get_rule", _I32, [_VP, _c_double_p, _c_double_p]),
     ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
+    ("bz_plan_rule_degree", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_plan_sync", _I32, [_VP, _VP]),
     ("bz_plan_set_timing", _I32, [_VP, _I32]),
@@ -283,6 +284,12 @@ def bz_plan_get_rule(plan: int, m: int):
     return d, w
 
 
+def bz_plan_rule_degree(plan: int) -> int:
+    t = _I32()
+    _check(lib().bz_plan_rule_degree(plan, ctypes.byref(t)))
+    return t.value
+
+
 def bz_plan_get_multipliers(plan: int, n: int, p: int, dim: int = 3):
     """FP64 host multipliers of pass p as ([k1][k2][k3] alpha, alpha'), or
     ([k1][k2] alpha, alpha') for a two-dimensional plan."""
@@ -429,6 +436,26 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def _out_rows(f, n_pts: int, ncells: int, scatter: bool) -> int:
+    """Rows an output must have: with BZ_SCATTER cell c is written at row
+    idx[c], which can be any row of f; otherwise rows 0..ncells."""
+    return f.numel() // n_pts if scatter else ncells
+
+
+def _output(out, f, n_pts: int, ncells: int, scatter: bool, dtype, cell_shape):
+    """Allocate the output, or check a caller-supplied one (contiguous, on the
+    GPU, of the right dtype, holding at least the rows the call writes)."""
+    torch = _torch()
+    rows = _out_rows(f, n_pts, ncells, scatter)
+    if out is None:
+        return torch.empty((rows,) + tuple(cell_shape), dtype=dtype, device=f.device)
+    if out.dtype != dtype or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous CUDA {dtype} tensor")
+    if out.numel() < rows * n_pts:
+        raise ValueError(f"out holds {out.numel() // n_pts} rows, the call writes up to row {rows - 1}")
+    return out
+
+
 def _stream(stream) -> int:
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -462,8 +489,7 @@ class Collider:
             ncells = idx.numel() if idx is not None else f.numel() // n3
         if idx is not None and (idx.dtype != torch.int32 or not idx.is_cuda):
             raise ValueError("idx must be a CUDA int32 tensor")
-        if out is None:
-            out = torch.empty((ncells,) + (self.n,) * self.dim, dtype=self.out_dtype, device=f.device)
+        out = _output(out, f, n3, ncells, scatter, self.out_dtype, (self.n,) * self.dim)
         fd = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
         bz_collide_batch(self.plan, _ptr(f), fd, _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
                          BZ_SCATTER if scatter else 0, _stream(stream))
@@ -478,8 +504,7 @@ class Collider:
                 raise ValueError("f and tr must be contiguous CUDA float64 tensors")
         if ncells is None:
             ncells = idx.numel() if idx is not None else f.numel() // self.n ** 3
-        if out is None:
-            out = torch.empty((ncells, self.n, self.n, self.n), dtype=torch.float64, device=f.device)
+        out = _output(out, f, self.n ** 3, ncells, scatter, torch.float64, (self.n,) * 3)
         d = BzImexDesc(dt, eps, _ptr(eps_cells))
         bz_imex_euler(self.plan, d, _ptr(f), _ptr(tr), _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
                       BZ_SCATTER if scatter else 0, _stream(stream))
@@ -551,8 +576,7 @@ def esbgk_collide(f, L: float, beta: float = -0.5, mu0: float = 1.0, idx=None, n
     """Q_ES(f) = nu (G[f] - f) for a batch of cells (bz_esbgk_collide)."""
     torch = _torch()
     n, ncells = _f64_cells(f, idx, ncells)
-    if out is None:
-        out = torch.empty((ncells, n, n, n), dtype=torch.float64, device=f.device)
+    out = _output(out, f, n ** 3, ncells, scatter, torch.float64, (n,) * 3)
     bz_esbgk_collide(BzEsbgkDesc(n, L, beta, mu0), _ptr(f), _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out),
                      BZ_SCATTER if scatter else 0, _stream(stream))
     return out
@@ -564,8 +588,7 @@ def esbgk_imex_euler(f, tr, L: float, dt: float, eps: float = 0.0, eps_cells=Non
     """One first-order IMEX step of the ES-BGK layer (bz_esbgk_imex_euler)."""
     torch = _torch()
     n, ncells = _f64_cells(f, idx, ncells)
-    if out is None:
-        out = torch.empty((ncells, n, n, n), dtype=torch.float64, device=f.device)
+    out = _output(out, f, n ** 3, ncells, scatter, torch.float64, (n,) * 3)
     bz_esbgk_imex_euler(BzEsbgkDesc(n, L, beta, mu0), BzImexDesc(dt, eps, _ptr(eps_cells)), _ptr(f), _ptr(tr),
                         _ptr(idx), ncells, _ptr(ncells_dev), _ptr(out), BZ_SCATTER if scatter else 0,
                         _stream(stream))

@@ -27,6 +27,7 @@ SOURCES = [
     ("mask.hip", ["-ffp-contract=off"]),
     ("kinetic.hip", []),
     ("plan.cpp", []),
+    ("design.cpp", []),
     ("server.cpp", []),
     ("step.cpp", []),
 ]

@@ -74,6 +74,7 @@ struct bz_plan {
   bz_plan* pad = nullptr;       // dealiased plans: the same operator on the 3n/2 grid (raw Q)
   std::vector<double> dirs;     // [m][3]
   std::vector<double> w;        // [m]
+  int rule_t = 0;               // antipodal design degree reached by a BZ_DIRS_DESIGN rule (0: not a DESIGN rule)
   // FP64 host tables in device layout [p][k2][k3][k1] x (a, a'), p < m1;
   // pass p = m carries (Bhat_M, 1) with weight -1.
   std::vector<double> mult;
@@ -111,6 +112,12 @@ void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s);
 bool kinetic_n_supported(int n);
 bz_status launch_imex_params(int n, double dv, const int32_t* idx, int ncells, const int32_t* ncells_dev,
                              const double* f, const double* tr, double dt, double* par, hipStream_t s);
+// direction rules (plan.cpp, design.cpp)
+void rule_spiral(int m, std::vector<double>& d, std::vector<double>& w);
+constexpr int kDesignMaxM = 256;
+int design_terms(int m);
+void rule_design(int m, std::vector<double>& d, std::vector<double>& w, int* t);
+int rule_degree(const std::vector<double>& d, const std::vector<double>& w);
 // plan helpers (plan.cpp)
 Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);

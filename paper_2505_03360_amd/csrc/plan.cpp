@@ -63,6 +63,8 @@ void rule_product(int a1, int a2, std::vector<double>& d, std::vector<double>& w
   for (double& x : w) x *= 2.0 * kPi / sum;
 }
 
+}  // namespace
+
 void rule_spiral(int m, std::vector<double>& d, std::vector<double>& w) {
   const double g = (1.0 + std::sqrt(5.0)) / 2.0;
   d.resize(3 * m);
@@ -76,6 +78,8 @@ void rule_spiral(int m, std::vector<double>& d, std::vector<double>& w) {
     d[3 * p + 2] = z;
   }
 }
+
+namespace {
 
 // ---------------------------------------------------------------- special functions
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
@@ -613,6 +617,10 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
     case BZ_DIRS_SPIRAL:
       rule_spiral(d.m, p->dirs, p->w);
       break;
+    case BZ_DIRS_DESIGN:
+      if (d.m < 2 || d.m > kDesignMaxM) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: DESIGN needs 2 <= m <= %d", kDesignMaxM); }
+      rule_design(d.m, p->dirs, p->w, &p->rule_t);
+      break;
     default:
       delete p;
       return fail(BZ_ERR_ARG, "bz_plan_create: bad dir_kind %d", d.dir_kind);
@@ -771,6 +779,14 @@ bz_status bz_plan_get_rule(const bz_plan* p, double* dirs, double* weights) {
   if (!p || !dirs || !weights) return fail(BZ_ERR_ARG, "bz_plan_get_rule: null argument");
   std::memcpy(dirs, p->dirs.data(), sizeof(double) * 3 * p->m);
   std::memcpy(weights, p->w.data(), sizeof(double) * p->m);
+  return BZ_OK;
+}
+
+bz_status bz_plan_rule_degree(const bz_plan* p, int32_t* t) {
+  clear_error();
+  if (!p || !t) return fail(BZ_ERR_ARG, "bz_plan_rule_degree: null argument");
+  if (p->dim == 2) return fail(BZ_ERR_UNSUPPORTED, "bz_plan_rule_degree: two-dimensional plans use the circle rule");
+  *t = p->rule_t > 0 ? p->rule_t : rule_degree(p->dirs, p->w);
   return BZ_OK;
 }
 
