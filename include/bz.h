@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define BZ_ABI_VERSION 3
+#define BZ_ABI_VERSION 4
 
 typedef int32_t bz_status;
 
@@ -429,6 +429,13 @@ bz_status bz_realizability_mask(const bz_mask_desc* desc, const double* rho, con
                                 const uint8_t* cell_flags, uint8_t* regime_out,
                                 int32_t* boltz_idx, int32_t* counts, double* diag, void* stream);
 
+/* Numeric status of a mask evaluation: waits for `stream`, then returns
+   BZ_ERR_NUMERIC if counts[1] (the mask's device status word, written by the
+   bz_realizability_mask call that took `counts`) reports cells with invalid
+   inputs, else BZ_OK.  Those cells kept their regime; the others are valid
+   results either way. */
+bz_status bz_mask_sync(const int32_t* counts, void* stream);
+
 /*
  * Serving: continuous batching of collision evaluations from several
  * concurrent simulations on one GPU (each dynamic re-partition of a
@@ -440,13 +447,20 @@ bz_status bz_realizability_mask(const bz_mask_desc* desc, const double* rho, con
  * an in-flight slot is free (a request that does not fit may be passed by at
  * most 8 later ones); admitted requests run on n_streams streams, so their
  * work overlaps on the device.  Plans are cached by descriptor (max_cells is
- * ignored) and evicted least-recently-used when idle and memory is short.
+ * ignored): the host plan is built on a builder thread the first time an
+ * operator is requested (meanwhile its requests wait and the others go
+ * ahead), its device tables are uploaded into the arena when a request needs
+ * them and evicted least-recently-used when idle and memory is short.  A
+ * request that does not fit while others run waits for them to finish.
  * Request buffers (f, idx, q) must stay valid and unmodified until
- * bz_serve_poll reports DONE or FAILED.  A request's result does not depend
- * on the other requests in flight.  A request whose descriptor is invalid
- * or whose workspace can never fit in the arena ends FAILED (err set) without
- * affecting the others; one whose output holds a non-finite value ends FAILED
- * with BZ_ERR_NUMERIC (its output is written).
+ * bz_serve_poll reports DONE or FAILED.  The server launches on its own
+ * streams: work the caller has queued that writes f or idx must be complete,
+ * or be covered by ready_event, before the request is admitted.  A request's
+ * result does not depend on the other requests in flight.  A request whose
+ * descriptor is invalid or whose workspace and tables can never fit in the
+ * arena together ends FAILED (err set) without affecting the others; one
+ * whose output holds a non-finite value ends FAILED with BZ_ERR_NUMERIC (its
+ * output is written).
  */
 typedef struct bz_server bz_server;
 
@@ -467,6 +481,11 @@ typedef struct {
   void* q;              /* device output as for bz_collide_batch */
   int32_t flags;        /* BZ_SCATTER */
   int32_t client_id;    /* caller's tag, unused by the server */
+  void* ready_event;    /* hipEvent_t or NULL: the request's kernels wait for it
+                           (hipStreamWaitEvent at admission), so a caller records
+                           it on the stream that produced f; it must not be
+                           re-recorded or destroyed before the request leaves
+                           the QUEUED state */
 } bz_request;
 
 enum { BZ_REQ_QUEUED = 0, BZ_REQ_ADMITTED = 1, BZ_REQ_DONE = 2, BZ_REQ_FAILED = 3 };
@@ -493,7 +512,12 @@ bz_status bz_serve_submit(bz_server* server, const bz_request* req, uint64_t* ti
    released), BZ_AGAIN (with the current state) while it is queued or running,
    BZ_ERR_ARG for an unknown ticket. */
 bz_status bz_serve_poll(bz_server* server, uint64_t ticket, bz_result* out);
-bz_status bz_server_stats(bz_server* server, bz_server_stats_t* out);
+/* Submit-to-done latency percentiles of the completed requests and the
+   completed cells per second since the first submission (any pointer may be
+   NULL). */
+bz_status bz_server_stats(bz_server* server, double* p50_ms, double* p99_ms, double* cells_per_s);
+/* The same figures with the request counters and arena use. */
+bz_status bz_server_stats_ex(bz_server* server, bz_server_stats_t* out);
 /* Run every queued and in-flight request to completion, then free the server. */
 bz_status bz_server_destroy(bz_server* server);
 

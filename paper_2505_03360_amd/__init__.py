@@ -70,7 +70,7 @@ class BzServerDesc(ctypes.Structure):
 class BzRequest(ctypes.Structure):
     _fields_ = [("plan", BzPlanDesc), ("f", ctypes.c_void_p), ("f_dtype", ctypes.c_int32),
                 ("idx", ctypes.c_void_p), ("ncells", ctypes.c_int32), ("q", ctypes.c_void_p),
-                ("flags", ctypes.c_int32), ("client_id", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("client_id", ctypes.c_int32), ("ready_event", ctypes.c_void_p)]
 
 
 class BzResult(ctypes.Structure):
@@ -116,7 +116,7 @@ class BzError(RuntimeError):
 
 
 _LIB = None
-ABI_VERSION = 3  # the struct layouts below match include/bz.h at this version
+ABI_VERSION = 4  # the struct layouts below match include/bz.h at this version
 
 # (name, restype, argtypes) for every symbol declared in include/bz.h
 _VP = ctypes.c_void_p
@@ -160,7 +160,9 @@ SIGNATURES = [
     ("bz_server_create", _I32, [ctypes.POINTER(BzServerDesc), ctypes.POINTER(_VP)]),
     ("bz_serve_submit", _I32, [_VP, ctypes.POINTER(BzRequest), ctypes.POINTER(ctypes.c_uint64)]),
     ("bz_serve_poll", _I32, [_VP, ctypes.c_uint64, ctypes.POINTER(BzResult)]),
-    ("bz_server_stats", _I32, [_VP, ctypes.POINTER(BzServerStats)]),
+    ("bz_server_stats", _I32, [_VP, _c_double_p, _c_double_p, _c_double_p]),
+    ("bz_server_stats_ex", _I32, [_VP, ctypes.POINTER(BzServerStats)]),
+    ("bz_mask_sync", _I32, [_VP, _VP]),
     ("bz_server_destroy", _I32, [_VP]),
     ("bz_step_create", _I32, [_VP, ctypes.POINTER(BzMaskDesc), ctypes.POINTER(BzStepBuffers), ctypes.POINTER(_VP)]),
     ("bz_step_launch", _I32, [_VP, _VP]),
@@ -402,14 +404,27 @@ def bz_serve_poll(server: int, ticket: int):
     return rc == BZ_OK, r
 
 
-def bz_server_stats(server: int) -> BzServerStats:
+def bz_server_stats(server: int):
+    """(p50_ms, p99_ms, cells_per_s) of the completed requests."""
+    v = [ctypes.c_double() for _ in range(3)]
+    _check(lib().bz_server_stats(server, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def bz_server_stats_ex(server: int) -> BzServerStats:
     st = BzServerStats()
-    _check(lib().bz_server_stats(server, ctypes.byref(st)))
+    _check(lib().bz_server_stats_ex(server, ctypes.byref(st)))
     return st
 
 
 def bz_server_destroy(server: int) -> None:
     _check(lib().bz_server_destroy(server))
+
+
+def bz_mask_sync(counts: int, stream: int = 0) -> None:
+    """Raises BzError(BZ_ERR_NUMERIC) if the mask call that wrote `counts`
+    found cells with invalid inputs."""
+    _check(lib().bz_mask_sync(counts, stream))
 
 
 def bz_step_create(plan: int, mask: BzMaskDesc, bufs: BzStepBuffers) -> int:
@@ -638,9 +653,13 @@ class Server:
         r.q = _ptr(q)
         r.flags = BZ_SCATTER if scatter else 0
         r.client_id = client_id
+        # the request's kernels wait for the work queued so far on the current stream (the writes of f, idx)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(f.device))
+        r.ready_event = ev.cuda_event
         t = bz_serve_submit(self.handle, r)
         if t is not None:
-            self._keep[t] = (f, q, idx, plan)
+            self._keep[t] = (f, q, idx, plan, ev)
         return t
 
     def poll(self, ticket):
@@ -650,7 +669,7 @@ class Server:
         return done, res
 
     def stats(self) -> BzServerStats:
-        return bz_server_stats(self.handle)
+        return bz_server_stats_ex(self.handle)
 
     def close(self):
         if self.handle:

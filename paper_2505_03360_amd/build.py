@@ -17,9 +17,6 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbz.so")
-# the FP32 vector issue-rate probe used by the measurement script, a library of its own
-PEAK_SRC = "peak_probe.hip"
-PEAK_LIB = os.path.join(PKG, "libbz_peak.so")
 
 SOURCES = [
     ("collide.hip", []),
@@ -68,15 +65,6 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
-    if os.path.exists(os.path.join(CSRC, PEAK_SRC)):
-        pobj = _compile((PEAK_SRC, []))
-        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", PEAK_LIB + ".tmp", pobj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-        os.replace(PEAK_LIB + ".tmp", PEAK_LIB)
-        if verbose:
-            print("built", PEAK_LIB)
     return LIB
 
 

@@ -26,11 +26,10 @@
 //          j3 slices, stage-B pencils along k2, a wave-local transpose,
 //          stage-C pencils along k1, products accumulated in registers; the
 //          projection or an IMEX update can run in the same kernel;
-//   chunked plain (FP32 plans that use no fused kernel): the stage-A pass writes K directions'
-//          intermediates at once, a second kernel runs stages B and C with
-//          the B->C transpose in LDS and accumulates over the chunk;
-//   plain (FP64): three pencil passes per direction through HBM, one thread
-//          per pencil;
+//   chunked plain (FP32 plans that use no fused kernel, and every FP64
+//          plan): the stage-A pass writes K directions' intermediates at
+//          once, a second kernel runs stages B and C with the B->C transpose
+//          in LDS and accumulates over the chunk;
 //   dealiased (either precision): f is resampled spectrally onto a 3n/2 grid,
 //          the plain or chunked passes run there, and the result is
 //          resampled back onto the n grid.

@@ -209,3 +209,16 @@ extern "C" bz_status bz_realizability_mask(const bz_mask_desc* d, const double* 
   if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_realizability_mask: launch failed: %s", hipGetErrorString(e));
   return BZ_OK;
 }
+
+extern "C" bz_status bz_mask_sync(const int32_t* counts, void* stream) {
+  bz::clear_error();
+  if (!counts) return bz::fail(BZ_ERR_ARG, "bz_mask_sync: null counts");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  int32_t host[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(host, counts, sizeof host, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bz::fail(BZ_ERR_DEVICE, "bz_mask_sync: %s", hipGetErrorString(e));
+  if (host[1] > 0)
+    return bz::fail(BZ_ERR_NUMERIC, "bz_realizability_mask: %d cells with invalid inputs (rho <= 0, T <= 0, eps < 0 "
+                    "or non-finite) kept their regime", int(host[1]));
+  return BZ_OK;
+}

@@ -8,11 +8,16 @@
 //     (ws_per_cell * cells bytes) fits in the caller's arena and an in-flight
 //     slot is free; a request that does not fit may be passed by later ones
 //     at most kMaxBypass times, after which admission waits for it;
-//   * keeps one plan per operator descriptor (tables uploaded once into the
-//     arena, evicted least-recently-used when idle and memory is short);
-//   * launches each admitted request on one of n_streams streams, so the
-//     work of concurrent requests overlaps on the device, and records an
-//     event after it;
+//   * keeps one plan per operator descriptor: the host plan (FP64 tables) is
+//     built on a builder thread, so a request that needs a new plan never
+//     holds up the admission or completion of the others, and stays cached
+//     on the host; its device tables are uploaded into the arena when a
+//     request needs them and evicted least-recently-used when idle and
+//     memory is short;
+//   * launches each admitted request on one of n_streams streams (after the
+//     request's ready event, if the caller gave one), so the work of
+//     concurrent requests overlaps on the device, and records an event
+//     after it;
 //   * polls those events, frees the workspace and timestamps completion.
 // A request's arithmetic does not depend on the other requests (each has its
 // own workspace; per-cell arithmetic is independent of the batch), so its
@@ -125,13 +130,22 @@ PlanKey make_key(const bz_plan_desc& d, int ncells) {
   return k;
 }
 
+enum { kPlanBuilding = 0, kPlanReady = 1, kPlanFailed = 2 };
+
+// Host plans built once per operator; device tables present while `resident`.
 struct CachedPlan {
   PlanKey key;
+  int max_cells = 1;      // capacity the host plan is built for (its strategy follows from it)
+  int state = kPlanBuilding;
+  bz_status err = BZ_OK;  // build error (kPlanFailed)
   bz_plan* plan = nullptr;
+  bool resident = false;
   size_t tables_off = 0, tables_bytes = 0;
   int inflight = 0;
   uint64_t last_use = 0;
 };
+// Host plans kept beyond those whose tables are resident.
+constexpr size_t kMaxHostPlans = 32;
 
 struct Req {
   uint64_t ticket = 0;
@@ -164,10 +178,14 @@ struct bz_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> inflight;
   std::vector<std::unique_ptr<CachedPlan>> plans;
+  std::deque<CachedPlan*> build_q;  // plans waiting for the builder thread
+  std::condition_variable build_cv;
+  uint64_t gen = 0;  // bumped by every event the scheduler may wait for (submit, build done, stop)
   uint64_t next_ticket = 1;
   int next_stream = 0;
-  bool stop = false;
-  std::thread th;
+  bool stop = false;          // drain and stop the scheduler
+  bool builder_stop = false;  // set once the scheduler has drained
+  std::thread th, builder;
   // statistics
   std::vector<double> lat_ms;
   uint64_t submitted = 0, completed = 0, failed = 0, cells_done = 0;
@@ -201,69 +219,94 @@ hipEvent_t take_event(bz_server* s) {
   return e;
 }
 
-// Evict idle cached plans (least recently used first) until `need` bytes can
-// be allocated or nothing idle is left.
+// Drop the device tables of idle resident plans (least recently used first)
+// until `need` bytes can be allocated or nothing idle is left; their host
+// plans stay cached.
 bool alloc_with_eviction(bz_server* s, size_t need, size_t* off) {
   while (!s->arena.alloc(need, off)) {
     CachedPlan* victim = nullptr;
-    size_t vi = 0;
-    for (size_t i = 0; i < s->plans.size(); ++i) {
-      CachedPlan* c = s->plans[i].get();
-      if (c->inflight == 0 && (!victim || c->last_use < victim->last_use)) {
-        victim = c;
-        vi = i;
-      }
-    }
+    for (auto& c : s->plans)
+      if (c->resident && c->inflight == 0 && (!victim || c->last_use < victim->last_use)) victim = c.get();
     if (!victim) return false;
     s->arena.release(victim->tables_off, victim->tables_bytes);
-    bz_plan_destroy(victim->plan);
-    s->plans.erase(s->plans.begin() + long(vi));
+    victim->resident = false;
   }
   return true;
 }
 
-// Find or build the plan of a request (called with the lock held; releases
-// it while the FP64 tables are built).
-CachedPlan* get_plan(bz_server* s, std::unique_lock<std::mutex>& lk, Req& q, bz_status* err) {
+// Destroy the least recently used idle host plans beyond kMaxHostPlans.
+void trim_host_plans(bz_server* s) {
+  while (s->plans.size() > kMaxHostPlans) {
+    size_t vi = s->plans.size();
+    for (size_t i = 0; i < s->plans.size(); ++i) {
+      const CachedPlan* c = s->plans[i].get();
+      if (c->state == kPlanBuilding || c->resident || c->inflight) continue;
+      if (vi == s->plans.size() || c->last_use < s->plans[vi]->last_use) vi = i;
+    }
+    if (vi == s->plans.size()) return;
+    bool queued = false;  // requests still name it: keep it
+    for (uint64_t id : s->queue) queued |= s->reqs[id].cp == s->plans[vi].get();
+    if (queued) return;
+    if (s->plans[vi]->plan) bz_plan_destroy(s->plans[vi]->plan);
+    s->plans.erase(s->plans.begin() + long(vi));
+  }
+}
+
+// The cached plan of a request's operator; a new one is handed to the
+// builder thread and comes back kPlanBuilding.
+CachedPlan* find_plan(bz_server* s, Req& q) {
   for (auto& c : s->plans)
     if (c->key == q.key) return c.get();
-  bz_plan_desc d = q.r.plan;
-  d.max_cells = std::max(1, q.r.ncells);
-  if (q.r.plan.dir_kind == BZ_DIRS_EXPLICIT) {
-    d.dirs = q.key.dirs.data();
-    d.weights = q.key.weights.data();
-  }
-  bz_plan* p = nullptr;
-  lk.unlock();
-  const bz_status st = bz_plan_create(&d, &p);
-  lk.lock();
-  if (st != BZ_OK) {
-    *err = st;
-    return nullptr;
-  }
-  for (auto& c : s->plans)  // built concurrently by nobody else, but be safe
-    if (c->key == q.key) {
-      bz_plan_destroy(p);
-      return c.get();
-    }
   auto c = std::make_unique<CachedPlan>();
   c->key = q.key;
-  c->plan = p;
-  c->tables_bytes = p->tables_bytes;
-  if (!alloc_with_eviction(s, c->tables_bytes, &c->tables_off)) {
-    bz_plan_destroy(p);
-    *err = BZ_ERR_NOMEM;
-    return nullptr;
-  }
-  const bz_status up = bz::upload_tables(p, s->arena.base + c->tables_off, s->upload);
-  if (up != BZ_OK) {
-    s->arena.release(c->tables_off, c->tables_bytes);
-    bz_plan_destroy(p);
-    *err = up;
-    return nullptr;
-  }
+  c->max_cells = std::max(1, q.r.ncells);
   s->plans.push_back(std::move(c));
-  return s->plans.back().get();
+  CachedPlan* cp = s->plans.back().get();
+  s->build_q.push_back(cp);
+  s->build_cv.notify_one();
+  return cp;
+}
+
+// Builder thread: FP64 tables of new plans on the host, outside the lock.
+void builder(bz_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->build_cv.wait(lk, [s] { return s->builder_stop || !s->build_q.empty(); });
+    if (s->build_q.empty()) return;  // the scheduler has drained: nothing left to build
+    CachedPlan* cp = s->build_q.front();
+    s->build_q.pop_front();
+    bz_plan_desc d = cp->key.d;
+    d.max_cells = cp->max_cells;
+    if (d.dir_kind == BZ_DIRS_EXPLICIT) {
+      d.dirs = cp->key.dirs.data();
+      d.weights = cp->key.weights.data();
+    }
+    lk.unlock();
+    bz_plan* p = nullptr;
+    const bz_status st = bz_plan_create(&d, &p);
+    lk.lock();
+    cp->plan = p;
+    cp->err = st;
+    cp->state = st == BZ_OK ? kPlanReady : kPlanFailed;
+    if (st == BZ_OK) cp->tables_bytes = p->tables_bytes;
+    s->gen += 1;
+    s->cv.notify_all();
+  }
+}
+
+// Upload the tables of a ready plan into the arena (called with the lock
+// held; the copy is short).  False if no room is left.
+bool make_resident(bz_server* s, CachedPlan* cp, bz_status* err) {
+  if (cp->resident) return true;
+  if (!alloc_with_eviction(s, cp->tables_bytes, &cp->tables_off)) return false;
+  const bz_status up = bz::upload_tables(cp->plan, s->arena.base + cp->tables_off, s->upload);
+  if (up != BZ_OK) {
+    s->arena.release(cp->tables_off, cp->tables_bytes);
+    *err = up;
+    return false;
+  }
+  cp->resident = true;
+  return true;
 }
 
 void reap(bz_server* s) {
@@ -286,34 +329,71 @@ void reap(bz_server* s) {
     else finish(s, q, BZ_REQ_DONE, BZ_OK);
     s->inflight[i] = s->inflight.back();
     s->inflight.pop_back();
+    s->gen += 1;
   }
 }
 
-void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
+// Workspace and, when needed, tables of request q.  With nothing in flight
+// every other plan is idle and evictable, so the only thing that can split
+// the free space is this plan's own tables: they are then dropped and placed
+// after the workspace (the descriptor check guarantees that both fit).
+bool place(bz_server* s, CachedPlan* cp, size_t ws, size_t* off, bz_status* err) {
+  cp->inflight += 1;  // pin the plan while allocating
+  bool ok = make_resident(s, cp, err) && alloc_with_eviction(s, ws, off);
+  if (!ok && *err == BZ_OK && s->inflight.empty()) {
+    if (cp->resident) {
+      s->arena.release(cp->tables_off, cp->tables_bytes);
+      cp->resident = false;
+    }
+    ok = alloc_with_eviction(s, ws, off);
+    if (ok && !make_resident(s, cp, err)) {
+      s->arena.release(*off, ws);
+      ok = false;
+    }
+  }
+  cp->inflight -= 1;
+  return ok;
+}
+
+// Admits what fits, in arrival order (bounded bypass); returns true if any
+// request changed state.
+bool admit(bz_server* s) {
+  bool progress = false;
   bool blocked = false;  // an earlier request ran out of bypasses
   for (size_t qi = 0; qi < s->queue.size() && !blocked;) {
-    if (int(s->inflight.size()) >= s->d.max_inflight) return;
+    if (int(s->inflight.size()) >= s->d.max_inflight) return progress;
     const uint64_t id = s->queue[qi];
     Req& q = s->reqs[id];
-    bz_status err = BZ_OK;
-    CachedPlan* cp = get_plan(s, lk, q, &err);
-    if (!cp) {
-      finish(s, q, BZ_REQ_FAILED, err);
+    CachedPlan* cp = q.cp ? q.cp : find_plan(s, q);
+    q.cp = cp;
+    if (cp->state == kPlanBuilding) {  // waits for the builder, passed by the others
+      ++qi;
+      continue;
+    }
+    if (cp->state == kPlanFailed) {
+      finish(s, q, BZ_REQ_FAILED, cp->err);
       s->queue.erase(s->queue.begin() + long(qi));
+      progress = true;
       continue;
     }
     const bz_plan* p = cp->plan;
     const size_t ws = p->ws_fixed + p->ws_per_cell * size_t(std::max(1, q.r.ncells));
-    if (ws + cp->tables_bytes > s->arena.bytes) {  // can never fit
+    if (bz::align256(ws) + bz::align256(cp->tables_bytes) > s->arena.bytes) {  // can never fit
       finish(s, q, BZ_REQ_FAILED, BZ_ERR_NOMEM);
       s->queue.erase(s->queue.begin() + long(qi));
+      progress = true;
       continue;
     }
     size_t off = 0;
-    cp->inflight += 1;  // pin the plan while allocating
-    const bool ok = alloc_with_eviction(s, ws, &off);
-    cp->inflight -= 1;
-    if (!ok) {
+    bz_status perr = BZ_OK;
+    if (!place(s, cp, ws, &off, &perr)) {
+      if (perr != BZ_OK) {  // device error while uploading the tables
+        finish(s, q, BZ_REQ_FAILED, perr);
+        s->queue.erase(s->queue.begin() + long(qi));
+        progress = true;
+        continue;
+      }
+      // no room while others run: wait for them (tables or workspace)
       q.bypassed += 1;
       if (q.bypassed > kMaxBypass) blocked = true;
       ++qi;
@@ -327,6 +407,9 @@ void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
     const int slot = s->free_slots.back();  // at most max_inflight requests are in flight
     s->free_slots.pop_back();
     s->status_host[slot] = 0;
+    if (lst == BZ_OK && q.r.ready_event &&
+        hipStreamWaitEvent(st, static_cast<hipEvent_t>(q.r.ready_event), 0) != hipSuccess)
+      lst = BZ_ERR_DEVICE;
     if (lst == BZ_OK && q.r.ncells > 0) {
       bz::launch_clear_status(b.ws, b.lay, st);
       lst = bz::launch_collide(p, b, q.r.f, q.r.f_dtype == BZ_FP32, q.r.idx, q.r.ncells, nullptr, q.r.q,
@@ -338,6 +421,7 @@ void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
     }
     if (lst == BZ_OK && hipEventRecord(ev, st) != hipSuccess) lst = BZ_ERR_DEVICE;
     s->queue.erase(s->queue.begin() + long(qi));
+    progress = true;
     if (lst != BZ_OK) {
       s->arena.release(off, ws);
       if (ev) s->event_pool.push_back(ev);
@@ -348,7 +432,6 @@ void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
     q.slot = slot;
     q.state = BZ_REQ_ADMITTED;
     q.t_admit = now_ns();
-    q.cp = cp;
     q.ws_off = off;
     q.ws_bytes = ws;
     q.ev = ev;
@@ -356,6 +439,7 @@ void admit(bz_server* s, std::unique_lock<std::mutex>& lk) {
     cp->last_use = q.t_admit;
     s->inflight.push_back(id);
   }
+  return progress;
 }
 
 void scheduler(bz_server* s) {
@@ -363,10 +447,14 @@ void scheduler(bz_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     reap(s);
-    admit(s, lk);
+    const uint64_t seen = s->gen;
+    admit(s);
+    trim_host_plans(s);
     if (s->stop && s->queue.empty() && s->inflight.empty()) break;
     if (s->inflight.empty()) {
-      s->cv.wait(lk, [s] { return s->stop || !s->queue.empty(); });
+      // nothing on the GPU: sleep until a submission, a finished build or stop
+      // (every queued request that could be admitted now has been)
+      s->cv.wait(lk, [s, seen] { return s->gen != seen; });
     } else {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -410,6 +498,7 @@ bz_status bz_server_create(const bz_server_desc* d, bz_server** out) {
   for (int i = d->max_inflight - 1; i >= 0; --i) s->free_slots.push_back(i);
   bz_server* raw = s.release();
   raw->th = std::thread(scheduler, raw);
+  raw->builder = std::thread(builder, raw);
   *out = raw;
   return BZ_OK;
 }
@@ -436,6 +525,7 @@ bz_status bz_serve_submit(bz_server* s, const bz_request* r, uint64_t* ticket) {
   *ticket = q.ticket;
   s->queue.push_back(q.ticket);
   s->reqs.emplace(q.ticket, std::move(q));
+  s->gen += 1;
   s->cv.notify_one();
   return BZ_OK;
 }
@@ -459,9 +549,9 @@ bz_status bz_serve_poll(bz_server* s, uint64_t ticket, bz_result* out) {
   return BZ_AGAIN;
 }
 
-bz_status bz_server_stats(bz_server* s, bz_server_stats_t* out) {
+bz_status bz_server_stats_ex(bz_server* s, bz_server_stats_t* out) {
   bz::clear_error();
-  if (!s || !out) return bz::fail(BZ_ERR_ARG, "bz_server_stats: null argument");
+  if (!s || !out) return bz::fail(BZ_ERR_ARG, "bz_server_stats_ex: null argument");
   std::lock_guard<std::mutex> g(s->mu);
   std::memset(out, 0, sizeof *out);
   out->submitted = s->submitted;
@@ -487,16 +577,34 @@ bz_status bz_server_stats(bz_server* s, bz_server_stats_t* out) {
   return BZ_OK;
 }
 
+bz_status bz_server_stats(bz_server* s, double* p50_ms, double* p99_ms, double* cells_per_s) {
+  bz_server_stats_t st;
+  const bz_status e = bz_server_stats_ex(s, &st);
+  if (e != BZ_OK) return e;
+  if (p50_ms) *p50_ms = st.p50_ms;
+  if (p99_ms) *p99_ms = st.p99_ms;
+  if (cells_per_s) *cells_per_s = st.cells_per_s;
+  return BZ_OK;
+}
+
 bz_status bz_server_destroy(bz_server* s) {
   bz::clear_error();
   if (!s) return BZ_OK;
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
+    s->gen += 1;
   }
   s->cv.notify_all();
-  if (s->th.joinable()) s->th.join();
-  for (auto& c : s->plans) bz_plan_destroy(c->plan);
+  if (s->th.joinable()) s->th.join();  // drains every request (the builder still builds for it)
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->builder_stop = true;
+  }
+  s->build_cv.notify_all();
+  if (s->builder.joinable()) s->builder.join();
+  for (auto& c : s->plans)
+    if (c->plan) bz_plan_destroy(c->plan);
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
   if (s->upload) (void)hipStreamDestroy(s->upload);

@@ -27,16 +27,23 @@ def run_both(d, rho, ux, uy, T, eps, regime, l1=None, flags=None, mode=0):
                                                     cu(regime, torch.uint8), cu(l1),
                                                     cu(flags, torch.uint8), with_diag=True)
     torch.cuda.synchronize()
+    try:  # invalid inputs surface as BZ_ERR_NUMERIC at the next sync
+        bz.bz_mask_sync(counts.data_ptr())
+        numeric = False
+    except bz.BzError as e:
+        assert e.code == bz.BZ_ERR_NUMERIC
+        numeric = True
     counts = counts.cpu().numpy()
     g_out = rout.cpu().numpy()
     g_idx = idx.cpu().numpy()[:counts[0]]
     g_diag = diag.cpu().numpy()
     o_out, o_idx, o_diag, o_bad = om.realizability_mask(d, rho, ux, uy, T, eps, regime, l1, flags)
-    return (g_out, g_idx, g_diag, counts), (o_out, o_idx, o_diag, o_bad)
+    return (g_out, g_idx, g_diag, counts, numeric), (o_out, o_idx, o_diag, o_bad)
 
 
 def assert_same(g, o):
-    (g_out, g_idx, g_diag, counts), (o_out, o_idx, o_diag, o_bad) = g, o
+    (g_out, g_idx, g_diag, counts, numeric), (o_out, o_idx, o_diag, o_bad) = g, o
+    assert numeric == (o_bad > 0)
     assert np.array_equal(g_out, o_out)
     assert np.array_equal(g_idx, o_idx)
     assert counts[0] == len(o_idx) and counts[1] == o_bad

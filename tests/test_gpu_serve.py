@@ -1,8 +1,13 @@
 """GPU tests of the serving runtime (bz_server_* / bz_serve_*): requests from
 several client threads with different grid sizes and cell counts; results are
-bitwise equal to a direct bz_collide_batch of the same operator, and a
-request's result is the same alone and in the mix; admission never exceeds
-the arena; failed requests do not disturb the others."""
+bitwise equal to a direct bz_collide_batch of the same operator, a request's
+result is the same alone and in the mix, and a sampled cell of every served
+request matches the FP64 oracle (per-cell error <= 1e-5 with the
+near-equilibrium floor, FP32 plans; moment drift <= 1e-12 after the FP64
+projection); admission never exceeds the arena, and a request that fits the
+arena only after its own plan's tables move is still admitted; failed
+requests do not disturb the others; a request waits for the caller's
+pending writes of its input."""
 import threading
 import time
 
@@ -10,6 +15,8 @@ import numpy as np
 import pytest
 
 import bz_inputs as gen
+from oracle import spectral
+from tests.gpu_util import oracle_plan
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -39,12 +46,35 @@ def inputs(n, cells, seed):
     return torch.from_numpy(gen.bimaxwellian_batch(cells, n, 8.0, seed=seed)).cuda()
 
 
+class OracleCells:
+    """FP64 oracle of the m = 8 spiral operator the serving tests request,
+    memoised per (input key, cell)."""
+
+    def __init__(self):
+        self.plans, self.memo = {}, {}
+
+    def check(self, key, f, q, cell, tol=1e-5):
+        n = f.shape[-1]
+        if n not in self.plans:
+            self.plans[n] = oracle_plan(n, rule="spiral", m=8)
+        if (key, cell) not in self.memo:
+            fc = f[cell].double().cpu().numpy()
+            qq, _, ql = spectral.collide_parts(fc, self.plans[n])
+            self.memo[(key, cell)] = (spectral.project(qq, n, 8.0), ql)
+        ref, loss = self.memo[(key, cell)]
+        got = q[cell].cpu().numpy()
+        err = spectral.rel_err(got, ref, loss)
+        assert err <= tol, (key, cell, err)
+        assert spectral.moment_drift(got, n, 8.0) <= 1e-12
+
+
 def test_serve_matches_direct_and_mix():
     import paper_2505_03360_amd as bz
     print("case serve mix", flush=True)
     srv = bz.Server(arena_bytes=2 << 30, max_inflight=6, n_streams=3)
     work = [(16, 5, 1), (24, 3, 2), (32, 4, 3), (16, 37, 4), (32, 9, 5), (24, 11, 6)]
     fs = {k: inputs(n, c, s) for k, (n, c, s) in enumerate(work)}
+    orc = OracleCells()
     # alone: one request at a time
     alone = {}
     for k, (n, c, s) in enumerate(work):
@@ -53,6 +83,7 @@ def test_serve_matches_direct_and_mix():
         assert res.state == bz.BZ_REQ_DONE and res.err == 0
         assert res.t_submit_ns <= res.t_admit_ns <= res.t_done_ns
         alone[k] = q.clone()
+        orc.check(k, fs[k], q, (3 * k) % c)
     # in the mix: all requests from three client threads at once, twice each
     outs = {}
 
@@ -75,12 +106,14 @@ def test_serve_matches_direct_and_mix():
     torch.cuda.synchronize()
     for (k, r), q in outs.items():
         assert torch.equal(q, alone[k]), (k, r)
+        orc.check(k, fs[k], q, (5 * k + 2 * r + 1) % work[k][1])
     # and equal to a direct call of the same operator
     for k, (n, c, s) in enumerate(work):
         col = bz.Collider(n, c, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=1)
         assert torch.equal(col(fs[k]), alone[k])
     st = srv.stats()
     assert st.completed == 18 and st.failed == 0 and st.p99_ms >= st.p50_ms > 0
+    assert bz.bz_server_stats(srv.handle) == (st.p50_ms, st.p99_ms, st.cells_per_s)
     srv.close()
 
 
@@ -146,4 +179,71 @@ def test_nonfinite_output_fails_only_its_request():
     t2 = srv.submit(good, qg, plan(bz, 16))
     r2 = wait(srv, t2)
     assert r2.state == bz.BZ_REQ_DONE and r2.err == 0
+    srv.close()
+
+
+def test_admission_moves_the_plans_own_tables():
+    """With nothing in flight, a request whose workspace fits the arena only
+    once its own plan's tables are moved (they split the free space) is
+    admitted: the tables are dropped, the workspace placed, the tables
+    uploaded again after it.  The request sequence builds that layout: plan
+    P1's tables at the front, then P2's, P1 evicted, and a large P2 request."""
+    import paper_2505_03360_amd as bz
+    print("case serve fragmented arena", flush=True)
+    n = 16
+    p1 = bz.make_plan_desc(n=n, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=1)
+    p2 = bz.make_plan_desc(n=n, L=8.0, m=6, dir_kind=bz.BZ_DIRS_ICOSA6, precision=1)
+
+    def sizes(pd, cells):
+        d = bz.make_plan_desc(n=n, L=8.0, m=pd.m, dir_kind=pd.dir_kind, precision=1, max_cells=cells)
+        h = bz.bz_plan_create(d)
+        tb, fixed, per = bz.bz_plan_device_bytes(h)
+        bz.bz_plan_destroy(h)
+        a = lambda x: (x + 255) // 256 * 256
+        return a(tb), lambda c: a(fixed + per * c)
+    t1, ws1 = sizes(p1, 1)
+    t2, ws2 = sizes(p2, 1)  # requests up to 256 cells share one plan (one chunk class)
+    c3 = 1
+    while ws2(c3) <= t1 + 4096:  # the large request's workspace exceeds P1's tables
+        c3 *= 2
+    assert c3 <= 256
+    arena = t2 + ws2(c3) + 256  # fits only as [workspace | P2 tables]
+    assert t1 + t2 + ws2(1) <= arena and ws2(c3) > arena - t1 - t2
+    srv = bz.Server(arena_bytes=arena, max_inflight=1, n_streams=1)
+    f = inputs(n, c3, 31)
+    q1 = torch.empty((1, n, n, n), dtype=torch.float64, device="cuda")
+    assert wait(srv, srv.submit(f[:1], q1, p1)).state == bz.BZ_REQ_DONE
+    q2 = torch.empty((1, n, n, n), dtype=torch.float64, device="cuda")
+    assert wait(srv, srv.submit(f[:1], q2, p2)).state == bz.BZ_REQ_DONE
+    q3 = torch.empty((c3, n, n, n), dtype=torch.float64, device="cuda")
+    r3 = wait(srv, srv.submit(f, q3, p2), timeout=60.0)
+    assert r3.state == bz.BZ_REQ_DONE and r3.err == 0
+    assert torch.equal(q3[:1], q2)
+    st = srv.stats()
+    assert st.arena_peak <= arena and st.completed == 3
+    srv.close()
+
+
+def test_request_waits_for_pending_input_writes():
+    """The input is produced by a long queue of kernels on the caller's stream
+    right before submission; the served result equals the one computed after a
+    full synchronisation."""
+    import paper_2505_03360_amd as bz
+    print("case serve ready event", flush=True)
+    n, c = 32, 64
+    src = inputs(n, c, 41)
+    f = torch.zeros_like(src)
+    srv = bz.Server(arena_bytes=1 << 30, max_inflight=2, n_streams=2)
+    pd = plan(bz, n)
+    q_ref = torch.empty((c, n, n, n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(50):  # a long chain of dependent writes ending in f == src
+        f.mul_(0.5).add_(src, alpha=0.5)
+    f.copy_(src)
+    q = torch.empty_like(q_ref)
+    t = srv.submit(f, q, pd)
+    assert wait(srv, t).state == bz.BZ_REQ_DONE
+    torch.cuda.synchronize()
+    assert wait(srv, srv.submit(src, q_ref, pd)).state == bz.BZ_REQ_DONE
+    assert torch.equal(q, q_ref)
     srv.close()

@@ -1,12 +1,27 @@
 """GPU test of the captured time step (bz_step_*): every replay of the graph
 (mask -> compaction -> collision over the device-counted Boltzmann cells ->
 regime feedback) matches the eager calls bit for bit, with the macro fields
-changing between replays; the regimes also match the mask oracle."""
+changing between replays; the regimes also match the mask oracle, and one
+Boltzmann cell of every replay matches the FP64 collision oracle (per-cell
+error <= 1e-5 with the near-equilibrium floor, moment drift <= 1e-12)."""
 import numpy as np
 import pytest
 
 import bz_inputs as gen
 from oracle import mask as om
+from oracle import spectral
+from tests.gpu_util import oracle_plan
+
+
+def check_cell_against_oracle(q, f, row, plan):
+    """Q of resident row `row` against the projected FP64 oracle."""
+    n = plan.n
+    qq, _, ql = spectral.collide_parts(f[row].double().cpu().numpy(), plan)
+    got = q[row].cpu().numpy()
+    err = spectral.rel_err(got, spectral.project(qq, n, plan.L), ql)
+    assert err <= 1e-5, (row, err)
+    assert spectral.moment_drift(got, n, plan.L) <= 1e-12
+
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -50,6 +65,7 @@ def test_graph_step_replays_match_eager():
     step = bz.bz_step_create(col.plan, md, b)
     stream = torch.cuda.current_stream().cuda_stream
     o_reg = np.ones((ny, nx), np.uint8)
+    oplan = oracle_plan(n, rule="spiral", m=8)
     for k in range(4):
         new = gen.bow_shock_field(nx, ny, step=k, seed=3)
         for t, a in zip(fields, new):
@@ -70,6 +86,7 @@ def test_graph_step_replays_match_eager():
         assert torch.equal(reg_graph, reg_eager)
         rows = i2[:cnt].long()
         assert torch.equal(q_graph[rows], q_eager[rows])
+        check_cell_against_oracle(q_graph, f, int(rows[(37 * k) % cnt]), oplan)
         # regimes against the oracle
         o_out, o_idx, _, _ = om.realizability_mask(d, *new, eps_np, o_reg)
         assert np.array_equal(reg_graph.cpu().numpy(), o_out)
@@ -134,6 +151,7 @@ def test_graph_step_with_kinetic_moments():
     b.kinetic_moments, b.kin_idx, b.kin_count = 1, kin_idx.data_ptr(), kin_count.data_ptr()
     step = bz.bz_step_create(col.plan, md, b)
     stream = torch.cuda.current_stream().cuda_stream
+    oplan = oracle_plan(n, rule="icosa6", m=6)
     for k in range(3):
         # eager reference: moments of the kinetic cells, mask, collision, feedback
         kin = torch.nonzero((reg_eager.view(-1) == 1) | (reg_eager.view(-1) == 2)).view(-1).int()
@@ -156,6 +174,7 @@ def test_graph_step_with_kinetic_moments():
         assert torch.equal(reg_graph, reg_eager)
         rows = i2[:cnt].long()
         assert torch.equal(q_graph[rows], q_eager[rows])
+        check_cell_against_oracle(q_graph, ft, int(rows[(4 * k) % cnt]), oplan)
     # the fluid strip kept the caller's fields; near-equilibrium kinetic cells went to the fluid layer
     assert torch.equal(fields_graph[0][:, :3], cu(rho * 1.01)[:, :3])
     final = reg_graph.cpu().numpy()
