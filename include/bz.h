@@ -164,7 +164,8 @@ bz_status bz_plan_device_bytes(const bz_plan* plan, size_t* tables, size_t* ws_f
    `stream`; the host tables stay alive inside the plan).  tables_dev must
    hold the `tables` bytes, ws_dev ws_bytes >= ws_fixed + ws_per_cell.  Both
    must be 256-byte aligned.  Calls that share a plan share its workspace:
-   they must be ordered on one stream. */
+   they must be ordered on one stream.  ws_dev NULL with ws_bytes 0 binds the
+   tables only (capacity 0; for bz_collide_batch_noalloc). */
 bz_status bz_plan_bind(bz_plan* plan, void* tables_dev, void* ws_dev, size_t ws_bytes,
                        void* stream);
 
@@ -229,6 +230,30 @@ bz_status bz_plan_get_multipliers(const bz_plan* plan, int32_t p, double* out);
 bz_status bz_collide_batch(const bz_plan* plan, const void* f, int32_t f_dtype,
                            const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
                            void* q, int32_t flags, void* stream);
+
+/*
+ * bz_collide_batch for callers that cannot allocate device memory or take a
+ * caller-owned workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same evaluation, arguments and
+ * results, with the workspace taken from a static 64 MiB device array that
+ * the library holds on every device it runs on until the process ends.  It
+ * allocates nothing.
+ * plan:    bound to its tables; the workspace binding may be absent
+ *          (bz_plan_bind with ws_dev NULL and ws_bytes 0) and is not used.
+ * ncells:  at most what fits: ws_fixed + ws_per_cell * ncells <= 64 MiB
+ *          (bz_plan_device_bytes; FP32 plans of more than 128 cells: 170
+ *          cells at n = 32, 1360 at n = 16), else BZ_ERR_NOMEM with the limit
+ *          in bz_last_error; with
+ *          ncells_dev, ncells is the bound the array must hold.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  Non-finite outputs
+ * are not reported (the array's status word is cleared by each call and
+ * bz_plan_sync does not read it).
+ */
+bz_status bz_collide_batch_noalloc(const bz_plan* plan, const void* f, int32_t f_dtype,
+                                   const int32_t* idx, int32_t ncells, const int32_t* ncells_dev,
+                                   void* q, int32_t flags, void* stream);
 
 /* Numeric status of the plan's evaluations: waits for `stream`, then returns
    BZ_ERR_NUMERIC (and clears the flag) if any bz_collide_batch /

@@ -137,6 +137,7 @@ SIGNATURES = [
     ("bz_plan_get_multipliers", _I32, [_VP, _I32, _c_double_p]),
     ("bz_plan_rule_degree", _I32, [_VP, ctypes.POINTER(_I32)]),
     ("bz_collide_batch", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
+    ("bz_collide_batch_noalloc", _I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _I32, _VP]),
     ("bz_plan_sync", _I32, [_VP, _VP]),
     ("bz_plan_set_timing", _I32, [_VP, _I32]),
     ("bz_cell_moments", _I32, [_I32, ctypes.c_double, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(BzMomentsOut),
@@ -308,6 +309,11 @@ def bz_plan_get_multipliers(plan: int, n: int, p: int, dim: int = 3):
 def bz_collide_batch(plan: int, f: int, f_dtype: int, idx: int, ncells: int, ncells_dev: int,
                      q: int, flags: int = 0, stream: int = 0) -> None:
     _check(lib().bz_collide_batch(plan, f, f_dtype, idx, ncells, ncells_dev, q, flags, stream))
+
+
+def bz_collide_batch_noalloc(plan: int, f: int, f_dtype: int, idx: int, ncells: int, ncells_dev: int,
+                             q: int, flags: int, stream: int = 0) -> None:
+    _check(lib().bz_collide_batch_noalloc(plan, f, f_dtype, idx, ncells, ncells_dev, q, flags, stream))
 
 
 def bz_cell_moments(n: int, L: float, f: int, f_dtype: int, idx: int, ncells: int, ncells_dev: int,

@@ -696,13 +696,21 @@ bz_status bz_plan_device_bytes(const bz_plan* p, size_t* tables, size_t* ws_fixe
 
 bz_status bz_plan_bind(bz_plan* p, void* tables_dev, void* ws_dev, size_t ws_bytes, void* stream) {
   clear_error();
-  if (!p || !tables_dev || !ws_dev) return fail(BZ_ERR_ARG, "bz_plan_bind: null argument");
+  if (!p || !tables_dev) return fail(BZ_ERR_ARG, "bz_plan_bind: null argument");
+  if (!ws_dev && ws_bytes) return fail(BZ_ERR_ARG, "bz_plan_bind: null workspace with ws_bytes > 0");
   if ((uintptr_t(tables_dev) & 255) || (uintptr_t(ws_dev) & 255))
     return fail(BZ_ERR_ARG, "bz_plan_bind: buffers must be 256-byte aligned");
-  if (ws_bytes < p->ws_fixed + p->ws_per_cell)
+  if (ws_dev && ws_bytes < p->ws_fixed + p->ws_per_cell)
     return fail(BZ_ERR_NOMEM, "bz_plan_bind: workspace %zu bytes < one cell (%zu)", ws_bytes, p->ws_fixed + p->ws_per_cell);
   const bz_status st = upload_tables(p, tables_dev, static_cast<hipStream_t>(stream));
   if (st != BZ_OK) return st;
+  if (!ws_dev) {  // tables only (bz_collide_batch_noalloc brings its own workspace)
+    p->capacity = 0;
+    p->tables_dev = tables_dev;
+    p->ws_dev = nullptr;
+    p->ws_bytes = 0;
+    return BZ_OK;
+  }
   const Binding b = make_binding(p, tables_dev, ws_dev, ws_bytes);
   static const int32_t kZero = 0;
   if (hipMemcpy(static_cast<char*>(ws_dev) + b.lay.status_off, &kZero, sizeof(kZero), hipMemcpyHostToDevice) != hipSuccess)
@@ -745,8 +753,8 @@ bz_status bz_plan_destroy(bz_plan* p) {
 bz_status bz_plan_capacity(const bz_plan* p, int32_t* cells) {
   clear_error();
   if (!p || !cells) return fail(BZ_ERR_ARG, "bz_plan_capacity: null argument");
-  if (!p->ws_dev) return fail(BZ_ERR_STATE, "bz_plan_capacity: plan not bound");
-  *cells = p->capacity;
+  if (!p->tables_dev) return fail(BZ_ERR_STATE, "bz_plan_capacity: plan not bound");
+  *cells = p->ws_dev ? p->capacity : 0;
   return BZ_OK;
 }
 

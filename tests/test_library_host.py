@@ -279,3 +279,22 @@ def test_spiral_and_product_rules_report_degree_one():
             assert bz.bz_plan_rule_degree(p) == 1
         finally:
             bz.bz_plan_destroy(p)
+
+
+def test_noalloc_refuses_beyond_the_static_array():
+    """bz_collide_batch_noalloc checks the workspace a call needs against its
+    64 MiB static array on the host, before anything touches the device (the
+    plan here is not even bound; the pointers are never dereferenced)."""
+    p = bz.bz_plan_create(bz.make_plan_desc(n=32, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=bz.BZ_FP64,
+                                            max_cells=64))
+    try:
+        tb, fixed, per = bz.bz_plan_device_bytes(p)
+        fits = ((64 << 20) - fixed) // per
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_collide_batch_noalloc(p, 1 << 20, bz.BZ_FP64, 0, fits + 1, 0, 1 << 20, 0, 0)
+        assert e.value.code == bz.BZ_ERR_NOMEM and f"at most {fits} cells" in str(e.value)
+        with pytest.raises(bz.BzError) as e:  # within the limit: refused only because the tables are not bound
+            bz.bz_collide_batch_noalloc(p, 1 << 20, bz.BZ_FP64, 0, fits, 0, 1 << 20, 0, 0)
+        assert e.value.code == bz.BZ_ERR_STATE
+    finally:
+        bz.bz_plan_destroy(p)
