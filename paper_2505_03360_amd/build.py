@@ -20,6 +20,7 @@ LIB = os.path.join(PKG, "libbz.so")
 
 SOURCES = [
     ("collide.hip", []),
+    ("noalloc.hip", []),
     ("collide2d.hip", []),
     ("mask.hip", ["-ffp-contract=off"]),
     ("kinetic.hip", []),
