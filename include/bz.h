@@ -71,7 +71,7 @@ enum {
 /* evaluation strategy */
 enum {
   BZ_XF_AUTO = 0,  /* fused kernel where one exists for (n, precision), else plain */
-  BZ_XF_FUSED = 1, /* fused per-direction kernel (FP32, n in {16, 32}) */
+  BZ_XF_FUSED = 1, /* fused per-direction kernel (FP32, n in {16, 24, 32}) */
   BZ_XF_PLAIN = 2  /* unfused pencil kernels through HBM (any precision, any n) */
 };
 
@@ -108,12 +108,13 @@ typedef struct {
                             (FP32: 8 up to 1024 cells, else 4; results do not
                             depend on it) */
   int32_t chunks;        /* fused path: direction chunks per cell, each a workgroup;
-                            0 = from max_cells (n = 32: 4 up to 64 cells, 2 up to
-                            128, else 1; n = 16: 4 up to 256, 2 up to 512), unless
+                            0 = from max_cells (n = 24, 32: 4 up to 64 cells, 2 up
+                            to 128, else 1; n = 16: 4 up to 256, 2 up to 512), unless
                             a tune table has a line for the plan.  Results depend
                             on the chunk count at FP32 rounding level only */
   int32_t slices;        /* fused path: j3 slices of the LDS transposes, 1 or 2
-                            (n = 16 only; n = 32 always uses 2); 0 = auto */
+                            (n = 16 either; n = 24 always uses 1, n = 32 2);
+                            0 = auto */
   int32_t dealias;       /* 0: circular convolution (l + m = k mod n);
                             1: truncated convolution without wrap-around
                             (l + m = k over the series' own modes), evaluated

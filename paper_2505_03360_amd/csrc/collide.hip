@@ -560,9 +560,12 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   constexpr int T = N * N / S;
   constexpr int W = N / S;
   constexpr int AB = W + 1;
-  static_assert(64 % N == 0 && W % (64 / N) == 0, "a wave owns whole j3 planes");
   // stage B: lane (k1, j3 % W) = (t % N, t / N); stage C: lane (j2, j3 % W) = (t % N, t / N).
-  // A wave's 64 lanes cover 64/N whole j3 planes, so B -> C stays inside the wave.
+  // When N divides 64, a wave's 64 lanes cover 64/N whole j3 planes and B -> C
+  // stays inside the wave; otherwise (N = 24) planes straddle waves and the
+  // transpose synchronises the workgroup.
+  constexpr bool wave_planes = (64 % N == 0) && (W % (64 / N) == 0);
+  static_assert(wave_planes || (T % 64 == 0 && S == 1), "planes that straddle waves need whole waves, one slice");
   const int tk = t % N, tj = t / N;
   const cx<float>* mp = a.mult + size_t(p) * N * N * N;
   const float wp = a.w[p];
@@ -704,10 +707,12 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     // writes (j2, k1) to row (N+1) j2 + k1 of the same planes (an injective
     // map; the row's residue j2 + k1 mod 32 keeps the writes, lanes on k1,
     // and the reads below, lanes on j2, on distinct banks)
-    wave_lds_sync();
+    if constexpr (wave_planes) wave_lds_sync();
+    else lds_barrier();
 #pragma unroll
     for (int j2 = 0; j2 < N; ++j2) lds[((N + 1) * j2 + tk) * AB + tj] = rb[j2];
-    wave_lds_sync();
+    if constexpr (wave_planes) wave_lds_sync();
+    else lds_barrier();
     cx<float> rc[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -740,9 +745,10 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 // wave's own planes, (j2, k1) at row (N+1) j2 + k1 (N-1 rows beyond the A->B
 // data): a wave synchronises only with itself between stages B and C.
 // Register budget: the paired (S = 2) kernels need up to 256 VGPRs (2 waves
-// per SIMD); N = 16 with one slice fits 4 waves per SIMD (128 VGPRs).
+// per SIMD); N = 16 with one slice fits 4 waves per SIMD (128 VGPRs); N = 24
+// (one slice, 576 threads, 120 KB of LDS) runs 9 waves per CU, 3 on one SIMD.
 template <int N, int S>
-constexpr int fused_min_waves() { return (N <= 16 && S == 1) ? 4 : 2; }
+constexpr int fused_min_waves() { return (N <= 16 && S == 1) ? 4 : (N == 24 ? 3 : 2); }
 
 template <int N, int S, bool IMEX>
 __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collide_fused(FusedArgs a) {
@@ -1248,9 +1254,11 @@ void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s) {
                      reinterpret_cast<int32_t*>(static_cast<char*>(ws) + lay.status_off), 0);
 }
 
-bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32); }
+bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 24 || n == 32); }
 
-bool fused_slices_supported(int n, int slices) { return (n == 16 && (slices == 1 || slices == 2)) || (n == 32 && slices == 2); }
+bool fused_slices_supported(int n, int slices) {
+  return (n == 16 && (slices == 1 || slices == 2)) || (n == 24 && slices == 1) || (n == 32 && slices == 2);
+}
 
 // Direction chunks per cell when the descriptor leaves them open.  One
 // workgroup per cell at n = 32 (143 KB of LDS: one per CU) fills the 256 CUs
@@ -1261,7 +1269,7 @@ bool fused_slices_supported(int n, int slices) { return (n == 16 && (slices == 1
 // kernels fit several workgroups per CU and gain up to 512 cells (64 cells
 // 1.87 -> 0.82 us per cell with four, 512 cells 0.27 -> 0.23 with two).
 int fused_default_chunks(int n, int max_cells) {
-  if (n == 32) return max_cells <= 64 ? 4 : (max_cells <= 128 ? 2 : 1);
+  if (n == 32 || n == 24) return max_cells <= 64 ? 4 : (max_cells <= 128 ? 2 : 1);
   if (n == 16) return max_cells <= 256 ? 4 : (max_cells <= 512 ? 2 : 1);
   return 1;
 }
@@ -1339,6 +1347,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       fw.fc = reinterpret_cast<float*>(ws + lay.y_off);
       fw.fc_stride = lay.y_cell / sizeof(float);
       if (p->n == 32) launch_fwd_fused<32, 2>(fw, ncells, s);
+      else if (p->n == 24) launch_fwd_fused<24, 1>(fw, ncells, s);
       else if (p->n == 16 && p->slices == 1) launch_fwd_fused<16, 1>(fw, ncells, s);
       else if (p->n == 16) launch_fwd_fused<16, 2>(fw, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);
@@ -1370,6 +1379,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
       }
       fused_projection = fa.fuse_project != 0;
       if (p->n == 32) launch_fused<32, 2>(fa, ncells, s);
+      else if (p->n == 24) launch_fused<24, 1>(fa, ncells, s);
       else if (p->n == 16 && p->slices == 1) launch_fused<16, 1>(fa, ncells, s);
       else if (p->n == 16) launch_fused<16, 2>(fa, ncells, s);
       else return fail(BZ_ERR_UNSUPPORTED, "fused path: n=%d", p->n);

@@ -652,7 +652,7 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   p->transform = (transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
   p->chunks = p->transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(p->n, d.max_cells)) : 1;
   if (p->chunks > p->m1) p->chunks = p->m1;
-  p->slices = slices > 0 ? slices : 2;
+  p->slices = slices > 0 ? slices : (p->n == 24 ? 1 : 2);
   if (p->transform == BZ_XF_FUSED && !fused_slices_supported(p->n, p->slices)) {
     delete p;
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel with %d slices for n=%d", slices, d.n);

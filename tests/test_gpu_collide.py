@@ -142,15 +142,45 @@ def test_n32_fp64_full_batch_sampled():
     assert err.max() <= 1e-12, err
 
 
-@pytest.mark.parametrize("n,precision,tol", [(24, 1, 1e-5), (24, 0, 1e-12), (48, 1, 1e-5)])
-def test_radix3_sizes(n, precision, tol):
-    label("radix3", n, precision)
+@pytest.mark.parametrize("n,precision,tol,transform", [(24, 1, 1e-5, 0), (24, 1, 1e-5, 2), (24, 0, 1e-12, 0),
+                                                       (48, 1, 1e-5, 0)])
+def test_radix3_sizes(n, precision, tol, transform):
+    import paper_2505_03360_amd as bz
+    label("radix3", n, precision, transform)
     f = gen.bimaxwellian_batch(2, n, 8.0, seed=n)
-    col = collider(n, 2, precision, rule="spiral", m=8)
+    col = collider(n, 2, precision, rule="spiral", m=8, transform=transform)
+    if n == 24 and precision == 1 and transform == 0:
+        assert col.transform == bz.BZ_XF_FUSED and bz.bz_plan_strategy(col.plan) == (bz.BZ_XF_FUSED, 4, 1)
     q = run(col, f)
     ref, loss = oracle_cells(f, oracle_plan(n, rule="spiral", m=8))
     err = cell_errors(q, ref, loss)
     assert err.max() <= tol, err
+
+
+def test_n24_fused_batch_sampled():
+    """N=24 on the fused kernel (one cell per workgroup, the whole 24^3 volume
+    in LDS, planes that straddle waves): 300 shock cells with the spherical
+    design (one chunk, projection in the epilogue), six cells against the
+    oracle, every 20th cell for conservation; the same cells through the
+    chunked plain path agree to the FP32 bound."""
+    import paper_2505_03360_amd as bz
+    from tests.gpu_util import oracle_plan_of
+    label("n24 fused batch")
+    f = gen.shock_batch(300, 24, 8.0, seed=24)
+    col = collider(24, 300, 1, rule="design")
+    assert bz.bz_plan_strategy(col.plan) == (bz.BZ_XF_FUSED, 1, 1)
+    q = run(col, f)
+    assert np.isfinite(q).all()
+    sample = [0, 57, 123, 199, 250, 299]
+    ref, loss = oracle_cells(f[sample], oracle_plan_of(col.plan, 24, 32))
+    err = cell_errors(q[sample], ref, loss)
+    print("max err", err.max(), flush=True)
+    assert err.max() <= 1e-5, err
+    for c in range(0, 300, 20):
+        assert spectral.moment_drift(q[c], 24, 8.0) <= 1e-12
+    plain = collider(24, 300, 1, rule="design", transform=2)
+    qp = run(plain, f)
+    assert cell_errors(qp[sample], ref, loss).max() <= 1e-5
 
 
 @pytest.mark.parametrize("gamma,transform", [(0.0, 1), (0.5, 2), (0.5, 1)])

@@ -43,7 +43,8 @@ def test_library_exports_every_declared_symbol():
     (dict(m=7, dir_kind=bz.BZ_DIRS_ICOSA6), bz.BZ_ERR_ARG),
     (dict(m=16, dir_kind=bz.BZ_DIRS_PRODUCT, a1=4, a2=3), bz.BZ_ERR_ARG),
     (dict(max_cells=0), bz.BZ_ERR_ARG),
-    (dict(n=24, transform=bz.BZ_XF_FUSED), bz.BZ_ERR_UNSUPPORTED),
+    (dict(n=48, transform=bz.BZ_XF_FUSED), bz.BZ_ERR_UNSUPPORTED),
+    (dict(n=24, transform=bz.BZ_XF_FUSED, slices=2), bz.BZ_ERR_UNSUPPORTED),
     (dict(precision=bz.BZ_FP64, transform=bz.BZ_XF_FUSED), bz.BZ_ERR_UNSUPPORTED),
 ])
 def test_plan_validation(kw, code):
