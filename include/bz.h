@@ -107,7 +107,9 @@ typedef struct {
                             the plain path's directions per chunk at n = 48
                             (FP32: 8 up to 1024 cells, else 4; results do not
                             depend on it) */
-  int32_t chunks;        /* fused path: direction chunks per cell, each a workgroup;
+  int32_t chunks;        /* plain path: directions per stage-A launch (1..8; 0 =
+                            from max_cells, as described under max_cells);
+                            fused path: direction chunks per cell, each a workgroup;
                             0 = from max_cells (n = 24, 32: 4 up to 64 cells, 2 up
                             to 128, else 1; n = 16: 4 up to 256, 2 up to 512), unless
                             a tune table has a line for the plan.  Results depend
@@ -181,14 +183,19 @@ bz_status bz_plan_transform(const bz_plan* plan, int32_t* transform);
 
 /* Strategy table written by the autotuner (paper_2505_03360_amd/autotune.py):
    one line per tuned case, "gfx950 n m precision max_cells transform chunks
-   slices us_per_cell".  bz_plan_create consults it when desc.transform is
-   BZ_XF_AUTO and desc.chunks and desc.slices are 0: it takes the line with the
-   same (n, m, precision) and the largest max_cells not above the plan's (else
-   the smallest).  NULL clears it.  The environment variable BZ_TUNE_TABLE
-   names a table when none is set. */
+   slices us_per_cell" (chunks: direction chunks per cell of the fused kernel,
+   or directions per launch pair of the plain path).  bz_plan_create consults
+   it when desc.transform is BZ_XF_AUTO and desc.chunks and desc.slices are 0:
+   it takes the line with the same (n, m, precision) and the largest max_cells
+   not above the plan's (else the smallest).  Which table: the one set here;
+   with NULL (the default), the file named by the environment variable
+   BZ_TUNE_TABLE, else tune_gfx950.txt in the directory of the library (the
+   table measured on an MI355X and shipped with it); "" uses none (the size
+   heuristics below). */
 bz_status bz_set_tune_table(const char* path);
 
-/* Strategy the plan resolved to: transform, chunks, slices. */
+/* Strategy the plan resolved to: transform, chunks (fused: direction chunks
+   per cell; plain: directions per stage-A launch), slices. */
 bz_status bz_plan_strategy(const bz_plan* plan, int32_t* transform, int32_t* chunks, int32_t* slices);
 
 /* Host copies of the plan's direction rule: dirs [m][3], weights [m]

@@ -2,14 +2,18 @@
 
 For each case (n, m, precision, cells) every strategy the library offers is
 timed on the GPU (HIP events around bz_collide_batch, the plan's own timing):
-the plain pencil passes, and the fused kernel with 1, 2, 4 or 8 direction
+the chunked plain pencil passes with 2, 4 or 8 directions per stage-A launch,
+and the fused kernel (FP32, n in {16, 24, 32}) with 1, 2, 4 or 8 direction
 chunks per cell and, for n = 16, one or two LDS slices.  A strategy is kept
 only if its output agrees with the plain FP64 path on the same batch
 (relative L2 over the batch <= 2e-5 in FP32, <= 1e-12 in FP64); the fastest
 kept strategy is written to a tune table that bz_plan_create reads (see
-bz_set_tune_table in include/bz.h).
+bz_set_tune_table in include/bz.h).  The table shipped beside the library,
+tune_gfx950.txt, was written by
 
-    python -m paper_2505_03360_amd.autotune --n 16 32 --m 32 --cells 1 16 256 --out tune_table.txt
+    python -m paper_2505_03360_amd.autotune --out paper_2505_03360_amd/tune_gfx950.txt
+
+(serving sizes n in {16, 24, 32, 48}, m = 32, 16 to 4096 cells, spherical design).
 """
 from __future__ import annotations
 
@@ -19,10 +23,13 @@ import os
 import paper_2505_03360_amd as bz
 
 
+FUSED_SLICES = {16: (1, 2), 24: (1,), 32: (2,)}
+
+
 def candidates(n: int, m: int, precision: int):
-    out = [(bz.BZ_XF_PLAIN, 1, 0)]
-    if precision == bz.BZ_FP32 and n in (16, 32):
-        for s in ((1, 2) if n == 16 else (2,)):
+    out = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
+    if precision == bz.BZ_FP32 and n in FUSED_SLICES:
+        for s in FUSED_SLICES[n]:
             for c in (1, 2, 4, 8):
                 if c <= m + 1:
                     out.append((bz.BZ_XF_FUSED, c, s))
@@ -35,7 +42,7 @@ def tune_case(n: int, m: int, precision: int, cells: int, reps: int = 5, L: floa
 
     import bz_inputs as gen
     f = torch.from_numpy(gen.bimaxwellian_batch(cells, n, L, seed=seed)).cuda()
-    kw = dict(L=L, m=m, dir_kind=bz.BZ_DIRS_SPIRAL)
+    kw = dict(L=L, m=m, dir_kind=bz.BZ_DIRS_DESIGN)
     ref = bz.Collider(n, cells, precision=bz.BZ_FP64, transform=bz.BZ_XF_PLAIN, **kw)(f)
     torch.cuda.synchronize()
     tol = 2e-5 if precision == bz.BZ_FP32 else 1e-12
@@ -52,6 +59,8 @@ def tune_case(n: int, m: int, precision: int, cells: int, reps: int = 5, L: floa
         bz.bz_plan_set_timing(col.plan, False)
         rows.append({"transform": x, "chunks": c, "slices": s, "ms": ms, "err": err, "ok": err <= tol})
         col.close()
+        del out
+        torch.cuda.empty_cache()
     ok = [r for r in rows if r["ok"]]
     if not ok:
         raise RuntimeError(f"no strategy passed parity for n={n} m={m} cells={cells}")
@@ -69,9 +78,9 @@ def write_table(path: str, entries):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, nargs="+", default=[16, 32])
+    ap.add_argument("--n", type=int, nargs="+", default=[16, 24, 32, 48])
     ap.add_argument("--m", type=int, default=32)
-    ap.add_argument("--cells", type=int, nargs="+", default=[1, 16, 256])
+    ap.add_argument("--cells", type=int, nargs="+", default=[16, 64, 128, 256, 512, 1024, 4096])
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--out", default=os.path.join(os.getcwd(), "tune_table.txt"))
     args = ap.parse_args()
@@ -82,7 +91,8 @@ def main():
             best, rows = tune_case(n, args.m, prec, cells)
             for r in rows:
                 print(f"n={n} cells={cells} transform={r['transform']} chunks={r['chunks']} "
-                      f"slices={r['slices']} {r['ms']:.4f} ms err={r['err']:.2e} {'ok' if r['ok'] else 'REJECTED'}")
+                      f"slices={r['slices']} {r['ms']:.4f} ms err={r['err']:.2e} {'ok' if r['ok'] else 'REJECTED'}",
+                      flush=True)
             entries.append((n, args.m, prec, cells) + best)
     write_table(args.out, entries)
     print("wrote", args.out)

@@ -71,6 +71,7 @@ struct bz_plan {
   int chunks = 1;               // direction chunks per cell (fused path)
   int slices = 2;               // j3 slices of the fused kernel's transposes
   int pchunk = 0;               // plain path: directions per chunk (stage-A volumes per cell)
+  int plain_k = 0;              // plain path: directions per chunk asked for (desc.chunks), 0 = by size
   bz_plan* pad = nullptr;       // dealiased plans: the same operator on the 3n/2 grid (raw Q)
   std::vector<double> dirs;     // [m][3]
   std::vector<double> w;        // [m]
@@ -124,4 +125,12 @@ bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
 bool fused_supported(int n, int fp32);
 bool fused_slices_supported(int n, int slices);
 int fused_default_chunks(int n, int max_cells);
+// evaluation strategy a three-dimensional descriptor resolves to at a capacity (plan.cpp)
+struct Strategy {
+  int transform = BZ_XF_PLAIN, chunks = 1, slices = 2, plain_k = 8;
+  bool operator==(const Strategy& o) const {
+    return transform == o.transform && chunks == o.chunks && slices == o.slices && plain_k == o.plain_k;
+  }
+};
+Strategy resolve_strategy(const bz_plan_desc& d, int max_cells);
 }  // namespace bz

@@ -2,6 +2,8 @@
 // FP64 multiplier tables of the fast spectral method (Sec. 4.4.1), the
 // inverse Gram matrix of the collision invariants, device binding and the
 // C-ABI entry points of the plan.
+#include <dlfcn.h>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -409,15 +411,27 @@ struct TuneChoice {
   bool found = false;
 };
 
+// The table shipped beside the library (tune_gfx950.txt in the directory of
+// libbz.so), written by the autotuner on an MI355X.
+std::string shipped_tune_table() {
+  Dl_info info{};
+  if (!dladdr(reinterpret_cast<void*>(&bz_set_tune_table), &info) || !info.dli_fname) return "";
+  std::string lib = info.dli_fname;
+  const size_t slash = lib.find_last_of('/');
+  return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tune_gfx950.txt";
+}
+
 TuneChoice tune_lookup(int n, int m, int precision, int max_cells) {
   std::string path;
+  bool set = false;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    if (g_tune_set) path = g_tune_path;
+    set = g_tune_set;
+    if (set) path = g_tune_path;
   }
-  if (path.empty()) {
+  if (!set) {
     const char* env = std::getenv("BZ_TUNE_TABLE");
-    if (env) path = env;
+    path = env ? std::string(env) : shipped_tune_table();
   }
   TuneChoice best;
   if (path.empty()) return best;
@@ -450,6 +464,35 @@ TuneChoice tune_lookup(int n, int m, int precision, int max_cells) {
   return best.found ? best : smallest;
 }
 
+}  // namespace
+
+// The evaluation strategy of a descriptor at a given capacity (three
+// dimensions): the descriptor's knobs, else the tune table's line, else the
+// size heuristics.  The server keys its cached plans by it.
+Strategy resolve_strategy(const bz_plan_desc& d, int max_cells) {
+  Strategy sg;
+  const int fp32 = d.precision == BZ_FP32;
+  const bool fused_ok = fused_supported(d.n, fp32);
+  int transform = d.transform, chunks = d.chunks, slices = d.slices;
+  if (transform == BZ_XF_AUTO && chunks == 0 && slices == 0) {
+    const TuneChoice tc = tune_lookup(d.n, d.m, d.precision, max_cells);
+    if (tc.found && (tc.transform == BZ_XF_PLAIN || (fused_ok && fused_slices_supported(d.n, tc.slices)))) {
+      transform = tc.transform;
+      chunks = tc.chunks;
+      slices = tc.slices;
+    }
+  }
+  sg.transform = (transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
+  sg.plain_k = (sg.transform == BZ_XF_PLAIN && chunks > 0) ? std::min(chunks, kPlainChunkMax)
+                                                           : plain_chunk(d.n, fp32 != 0, max_cells);
+  sg.chunks = sg.transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(d.n, max_cells)) : 1;
+  if (sg.chunks > d.m + 1) sg.chunks = d.m + 1;
+  sg.slices = slices > 0 ? slices : (d.n == 24 ? 1 : 2);
+  return sg;
+}
+
+namespace {
+
 void layout(bz_plan* p) {
   const size_t n3 = size_t(p->n) * p->n * p->n;
   const size_t es = p->fp32 ? 4 : 8;
@@ -464,7 +507,7 @@ void layout(bz_plan* p) {
   // chunked plain path: a chunk of pchunk directions shares the stage-A output
   // (one volume per direction); fused: an FP32 copy of f in the collision
   // kernel's loss-pass order
-  p->pchunk = fused ? 0 : plain_chunk(p->n, p->fp32 != 0, p->d.max_cells);
+  p->pchunk = fused ? 0 : (p->plain_k > 0 ? p->plain_k : plain_chunk(p->n, p->fp32 != 0, p->d.max_cells));
   p->ws.y_cell = fused ? align256(n3 * sizeof(float)) : align256(n3 * 2 * es * p->pchunk);
   p->ws.acc_cell = align256(n3 * es * acc_chunks);
   p->ws.par_cell = sizeof(double) * bzk::kImexPar * 2;  // per-cell IMEX parameters (128 B)
@@ -640,22 +683,14 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
     delete p;
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel for n=%d precision=%s", d.n, p->fp32 ? "fp32" : "fp64");
   }
-  int transform = d.transform, chunks = d.chunks, slices = d.slices;
-  if (transform == BZ_XF_AUTO && chunks == 0 && slices == 0) {
-    const TuneChoice tc = tune_lookup(d.n, d.m, d.precision, d.max_cells);
-    if (tc.found && (tc.transform == BZ_XF_PLAIN || (fused_ok && fused_slices_supported(d.n, tc.slices)))) {
-      transform = tc.transform;
-      chunks = tc.chunks;
-      slices = tc.slices;
-    }
-  }
-  p->transform = (transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
-  p->chunks = p->transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(p->n, d.max_cells)) : 1;
-  if (p->chunks > p->m1) p->chunks = p->m1;
-  p->slices = slices > 0 ? slices : (p->n == 24 ? 1 : 2);
+  const Strategy sg = resolve_strategy(d, d.max_cells);
+  p->transform = sg.transform;
+  p->plain_k = sg.transform == BZ_XF_PLAIN ? sg.plain_k : 0;
+  p->chunks = sg.chunks;
+  p->slices = sg.slices;
   if (p->transform == BZ_XF_FUSED && !fused_slices_supported(p->n, p->slices)) {
     delete p;
-    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel with %d slices for n=%d", slices, d.n);
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel with %d slices for n=%d", p->slices, d.n);
   }
   if (d.dealias) {
     // the padded operator: same box, R, kernel and rule on 3n/2 points, raw Q in the plan precision
@@ -768,7 +803,7 @@ bz_status bz_plan_transform(const bz_plan* p, int32_t* transform) {
 bz_status bz_set_tune_table(const char* path) {
   clear_error();
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_set = path != nullptr;
+  g_tune_set = path != nullptr;  // NULL: back to BZ_TUNE_TABLE or the shipped table; "": none
   g_tune_path = path ? path : "";
   return BZ_OK;
 }
@@ -777,7 +812,7 @@ bz_status bz_plan_strategy(const bz_plan* p, int32_t* transform, int32_t* chunks
   clear_error();
   if (!p) return fail(BZ_ERR_ARG, "bz_plan_strategy: null plan");
   if (transform) *transform = p->transform;
-  if (chunks) *chunks = p->chunks;
+  if (chunks) *chunks = p->transform == BZ_XF_PLAIN ? p->pchunk : p->chunks;
   if (slices) *slices = p->slices;
   return BZ_OK;
 }

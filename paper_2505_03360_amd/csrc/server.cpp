@@ -98,9 +98,9 @@ struct Arena {
 struct PlanKey {
   bz_plan_desc d{};
   std::vector<double> dirs, weights;
-  int chunk_class = 0;  // chunk choices that follow from the request size (plans differ by them)
+  bz::Strategy sg;  // strategy at the request's size (tune table or heuristics): plans differ by it
   bool operator==(const PlanKey& o) const {
-    return chunk_class == o.chunk_class && d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
+    return sg == o.sg && d.n == o.d.n && d.L == o.d.L && d.R == o.d.R && d.gamma == o.d.gamma &&
            d.kernel_c == o.d.kernel_c && d.m == o.d.m && d.dir_kind == o.d.dir_kind && d.a1 == o.d.a1 &&
            d.a2 == o.d.a2 && d.precision == o.d.precision && d.transform == o.d.transform &&
            d.project == o.d.project && d.chunks == o.d.chunks && d.slices == o.d.slices &&
@@ -112,14 +112,10 @@ struct PlanKey {
 PlanKey make_key(const bz_plan_desc& d, int ncells) {
   PlanKey k;
   k.d = d;
-  // a plan picks its direction chunks (fused path, when left open) and its
-  // plain-path chunk from its capacity: requests of different size classes get
-  // (and cache) different plans
-  if (d.dim != 2) {
-    const int nc = std::max(1, ncells);
-    if (d.chunks == 0) k.chunk_class = bz::fused_default_chunks(d.n, nc);
-    k.chunk_class = k.chunk_class * 16 + bz::plain_chunk(d.n, d.precision == BZ_FP32, nc);
-  }
+  // a plan picks its strategy from its capacity (tune table or size
+  // heuristics): requests that resolve to different strategies get (and cache)
+  // different plans, so a request's arithmetic depends only on its own size
+  if (d.dim != 2) k.sg = bz::resolve_strategy(d, std::max(1, ncells));
   k.d.max_cells = 0;
   k.d.dirs = nullptr;
   k.d.weights = nullptr;

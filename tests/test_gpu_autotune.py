@@ -18,12 +18,12 @@ def test_autotune_small_case(tmp_path):
     from paper_2505_03360_amd.autotune import tune_case, write_table
     print("case autotune", flush=True)
     best, rows = tune_case(16, 8, bz.BZ_FP32, 6, reps=2)
-    assert len(rows) == 9 and all(r["ok"] for r in rows), rows
+    assert len(rows) == 11 and all(r["ok"] for r in rows), rows
     write_table(str(tmp_path / "t.txt"), [(16, 8, bz.BZ_FP32, 6) + best])
     bz.bz_set_tune_table(str(tmp_path / "t.txt"))
     try:
-        p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=6))
-        assert bz.bz_plan_strategy(p)[0] == best[0]
+        p = bz.bz_plan_create(bz.make_plan_desc(n=16, m=8, dir_kind=bz.BZ_DIRS_DESIGN, max_cells=6))
+        assert bz.bz_plan_strategy(p)[:2] == best[:2]
         bz.bz_plan_destroy(p)
     finally:
         bz.bz_set_tune_table(None)

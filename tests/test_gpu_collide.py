@@ -142,15 +142,15 @@ def test_n32_fp64_full_batch_sampled():
     assert err.max() <= 1e-12, err
 
 
-@pytest.mark.parametrize("n,precision,tol,transform", [(24, 1, 1e-5, 0), (24, 1, 1e-5, 2), (24, 0, 1e-12, 0),
+@pytest.mark.parametrize("n,precision,tol,transform", [(24, 1, 1e-5, 1), (24, 1, 1e-5, 2), (24, 0, 1e-12, 0),
                                                        (48, 1, 1e-5, 0)])
 def test_radix3_sizes(n, precision, tol, transform):
     import paper_2505_03360_amd as bz
     label("radix3", n, precision, transform)
     f = gen.bimaxwellian_batch(2, n, 8.0, seed=n)
     col = collider(n, 2, precision, rule="spiral", m=8, transform=transform)
-    if n == 24 and precision == 1 and transform == 0:
-        assert col.transform == bz.BZ_XF_FUSED and bz.bz_plan_strategy(col.plan) == (bz.BZ_XF_FUSED, 4, 1)
+    if n == 24 and transform == 1:  # fused, direction chunks from the size (four at two cells)
+        assert bz.bz_plan_strategy(col.plan) == (bz.BZ_XF_FUSED, 4, 1)
     q = run(col, f)
     ref, loss = oracle_cells(f, oracle_plan(n, rule="spiral", m=8))
     err = cell_errors(q, ref, loss)
@@ -167,7 +167,7 @@ def test_n24_fused_batch_sampled():
     from tests.gpu_util import oracle_plan_of
     label("n24 fused batch")
     f = gen.shock_batch(300, 24, 8.0, seed=24)
-    col = collider(24, 300, 1, rule="design")
+    col = collider(24, 300, 1, rule="design", transform=1)
     assert bz.bz_plan_strategy(col.plan) == (bz.BZ_XF_FUSED, 1, 1)
     q = run(col, f)
     assert np.isfinite(q).all()

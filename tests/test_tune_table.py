@@ -20,19 +20,63 @@ def test_tune_table_selects_strategy(tmp_path):
         assert strategy(16, 500) == (bz.BZ_XF_FUSED, 1, 1)
         assert strategy(32, 1)[0] == bz.BZ_XF_PLAIN             # smallest entry when none fits
         assert strategy(16, 64, chunks=2) == (bz.BZ_XF_FUSED, 2, 2)  # explicit knobs win
-        assert strategy(24, 64)[0] == bz.BZ_XF_PLAIN            # no fused kernel for n = 24
+        assert strategy(24, 64)[0] == bz.BZ_XF_FUSED            # no line for n = 24: heuristics
+        assert strategy(32, 16)[:2] == (bz.BZ_XF_PLAIN, 1)       # plain: chunks = directions per launch
     finally:
         bz.bz_set_tune_table(None)
-    # without a table the plan sizes its direction chunks from max_cells
-    for n, cells, chunks in [(16, 1, 4), (16, 256, 4), (16, 512, 2), (16, 2048, 1),
-                             (32, 64, 4), (32, 128, 2), (32, 256, 1)]:
-        p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=cells))
-        assert bz.bz_plan_strategy(p) == (bz.BZ_XF_FUSED, chunks, 2), (n, cells)
+    # without a table ("") the plan sizes its direction chunks from max_cells
+    bz.bz_set_tune_table("")
+    try:
+        for n, cells, chunks, slices in [(16, 1, 4, 2), (16, 256, 4, 2), (16, 512, 2, 2), (16, 2048, 1, 2),
+                                         (24, 64, 4, 1), (24, 300, 1, 1), (32, 64, 4, 2), (32, 128, 2, 2),
+                                         (32, 256, 1, 2)]:
+            p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=cells))
+            assert bz.bz_plan_strategy(p) == (bz.BZ_XF_FUSED, chunks, slices), (n, cells)
+            bz.bz_plan_destroy(p)
+        for n, prec, cells, k in [(48, bz.BZ_FP32, 1024, 8), (48, bz.BZ_FP32, 4096, 4), (48, bz.BZ_FP64, 64, 4),
+                                  (32, bz.BZ_FP64, 64, 8)]:
+            p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=cells,
+                                                    precision=prec))
+            assert bz.bz_plan_strategy(p)[:2] == (bz.BZ_XF_PLAIN, k), (n, prec, cells)
+            bz.bz_plan_destroy(p)
+    finally:
+        bz.bz_set_tune_table(None)
+
+
+def test_plain_directions_per_launch_knob():
+    for k in (1, 2, 5, 8):
+        p = bz.bz_plan_create(bz.make_plan_desc(n=48, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=16, chunks=k,
+                                                transform=bz.BZ_XF_PLAIN))
+        tb, fixed, per = bz.bz_plan_device_bytes(p)
+        assert bz.bz_plan_strategy(p)[:2] == (bz.BZ_XF_PLAIN, k)
         bz.bz_plan_destroy(p)
+        assert per >= k * 48 ** 3 * 8  # k stage-A volumes of complex FP32 per cell
+
+
+def test_shipped_table_is_read_by_default():
+    """The library reads tune_gfx950.txt beside libbz.so when no table is set:
+    every line parses, and a plan at a tuned size resolves to the line's
+    strategy."""
+    import os
+    path = os.path.join(os.path.dirname(bz.LIB_PATH), "tune_gfx950.txt")
+    if not os.path.exists(path):
+        return
+    lines = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert lines and all(ln[0] == "gfx950" and len(ln) == 9 for ln in lines)
+    bz.bz_set_tune_table(None)
+    for ln in lines:
+        n, m, prec, cells, x, c, s = (int(v) for v in ln[1:8])
+        p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=m, dir_kind=bz.BZ_DIRS_DESIGN, max_cells=cells,
+                                                precision=prec))
+        got = bz.bz_plan_strategy(p)
+        bz.bz_plan_destroy(p)
+        assert got[0] == x and got[1] == c and (x == bz.BZ_XF_PLAIN or got[2] == s), (ln, got)
 
 
 def test_candidate_set():
+    plain = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
     c16 = candidates(16, 32, bz.BZ_FP32)
-    assert (bz.BZ_XF_PLAIN, 1, 0) in c16 and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 9
-    assert candidates(24, 32, bz.BZ_FP32) == [(bz.BZ_XF_PLAIN, 1, 0)]
-    assert candidates(32, 32, bz.BZ_FP64) == [(bz.BZ_XF_PLAIN, 1, 0)]
+    assert c16[:3] == plain and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 11
+    assert candidates(24, 32, bz.BZ_FP32) == plain + [(bz.BZ_XF_FUSED, c, 1) for c in (1, 2, 4, 8)]
+    assert candidates(48, 32, bz.BZ_FP32) == plain
+    assert candidates(32, 32, bz.BZ_FP64) == plain
