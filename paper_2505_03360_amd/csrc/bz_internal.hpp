@@ -132,5 +132,6 @@ struct Strategy {
     return transform == o.transform && chunks == o.chunks && slices == o.slices && plain_k == o.plain_k;
   }
 };
-Strategy resolve_strategy(const bz_plan_desc& d, int max_cells);
+Strategy resolve_strategy(const bz_plan_desc& d, int max_cells, size_t ws_budget = ~size_t(0));
+size_t plain_ws_per_cell(int n, bool fp32, int K);
 }  // namespace bz

@@ -469,7 +469,15 @@ TuneChoice tune_lookup(int n, int m, int precision, int max_cells) {
 // The evaluation strategy of a descriptor at a given capacity (three
 // dimensions): the descriptor's knobs, else the tune table's line, else the
 // size heuristics.  The server keys its cached plans by it.
-Strategy resolve_strategy(const bz_plan_desc& d, int max_cells) {
+// Workspace bytes per cell of the chunked plain path with K directions per
+// stage-A launch (the layout below without a dealiased sub-plan).
+size_t plain_ws_per_cell(int n, bool fp32, int K) {
+  const size_t n3 = size_t(n) * n * n, es = fp32 ? 4 : 8;
+  return align256(n3 * 2 * es) + align256(n3 * 2 * es * size_t(K)) + align256(n3 * es) +
+         sizeof(double) * bzk::kImexPar * 2;
+}
+
+Strategy resolve_strategy(const bz_plan_desc& d, int max_cells, size_t ws_budget) {
   Strategy sg;
   const int fp32 = d.precision == BZ_FP32;
   const bool fused_ok = fused_supported(d.n, fp32);
@@ -488,6 +496,10 @@ Strategy resolve_strategy(const bz_plan_desc& d, int max_cells) {
   sg.chunks = sg.transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(d.n, max_cells)) : 1;
   if (sg.chunks > d.m + 1) sg.chunks = d.m + 1;
   sg.slices = slices > 0 ? slices : (d.n == 24 ? 1 : 2);
+  // fewer stage-A volumes per cell when the workspace of max_cells cells would exceed the budget
+  if (sg.transform == BZ_XF_PLAIN && !d.dealias)
+    while (sg.plain_k > 1 && plain_ws_per_cell(d.n, fp32 != 0, sg.plain_k) * size_t(std::max(1, max_cells)) > ws_budget)
+      sg.plain_k /= 2;
   return sg;
 }
 

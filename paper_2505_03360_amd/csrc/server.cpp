@@ -109,13 +109,19 @@ struct PlanKey {
   }
 };
 
-PlanKey make_key(const bz_plan_desc& d, int ncells) {
+PlanKey make_key(const bz_plan_desc& d, int ncells, size_t arena_bytes) {
   PlanKey k;
   k.d = d;
   // a plan picks its strategy from its capacity (tune table or size
-  // heuristics): requests that resolve to different strategies get (and cache)
-  // different plans, so a request's arithmetic depends only on its own size
-  if (d.dim != 2) k.sg = bz::resolve_strategy(d, std::max(1, ncells));
+  // heuristics; the plain path's stage-A volumes per cell so that the
+  // workspace fits the arena): requests that resolve to different strategies
+  // get (and cache) different plans, built with that strategy as explicit
+  // knobs, so a request's arithmetic depends only on its own size
+  if (d.dim != 2) {
+    const size_t n3 = size_t(d.n) * d.n * d.n, es = d.precision == BZ_FP32 ? 4 : 8;
+    const size_t tables = size_t(std::max(1, d.m) + 1) * n3 * 2 * es + 4096;
+    k.sg = bz::resolve_strategy(d, std::max(1, ncells), arena_bytes > tables ? arena_bytes - tables : 0);
+  }
   k.d.max_cells = 0;
   k.d.dirs = nullptr;
   k.d.weights = nullptr;
@@ -273,6 +279,11 @@ void builder(bz_server* s) {
     s->build_q.pop_front();
     bz_plan_desc d = cp->key.d;
     d.max_cells = cp->max_cells;
+    if (d.dim != 2 && !d.dealias) {  // the strategy of the key, as explicit knobs
+      d.transform = cp->key.sg.transform;
+      d.chunks = cp->key.sg.transform == BZ_XF_PLAIN ? cp->key.sg.plain_k : cp->key.sg.chunks;
+      d.slices = cp->key.sg.transform == BZ_XF_PLAIN ? 0 : cp->key.sg.slices;
+    }
     if (d.dir_kind == BZ_DIRS_EXPLICIT) {
       d.dirs = cp->key.dirs.data();
       d.weights = cp->key.weights.data();
@@ -514,7 +525,7 @@ bz_status bz_serve_submit(bz_server* s, const bz_request* r, uint64_t* ticket) {
   Req q;
   q.ticket = s->next_ticket++;
   q.r = *r;
-  q.key = make_key(r->plan, r->ncells);
+  q.key = make_key(r->plan, r->ncells, s->arena.bytes);
   q.t_submit = now_ns();
   if (s->submitted == 0) s->t_first_submit = q.t_submit;
   s->submitted += 1;
