@@ -72,7 +72,12 @@ enum {
 enum {
   BZ_XF_AUTO = 0,  /* fused kernel where one exists for (n, precision), else plain */
   BZ_XF_FUSED = 1, /* fused per-direction kernel (FP32, n in {16, 24, 32}) */
-  BZ_XF_PLAIN = 2  /* unfused pencil kernels through HBM (any precision, any n) */
+  BZ_XF_PLAIN = 2, /* unfused pencil kernels through HBM (any precision, any n) */
+  BZ_XF_DFT_GEMM = 3 /* the plain path with its last length-n inverse transforms
+                        (along k1) done as dense DFT matrix products on the matrix
+                        cores (FP32 MFMA, exact FP32 products; FP32 plans, n in
+                        {16, 32, 48}): 8n flop per point against the FFT's
+                        5 log2 n, kept only where the autotuner measures it faster */
 };
 
 /* bz_collide_batch flags */

@@ -20,7 +20,7 @@ BZ_OK, BZ_AGAIN = 0, 1
 BZ_ERR_ARG, BZ_ERR_UNSUPPORTED, BZ_ERR_DEVICE, BZ_ERR_NOMEM, BZ_ERR_STATE, BZ_ERR_NUMERIC = -1, -2, -3, -4, -5, -6
 BZ_FP64, BZ_FP32 = 0, 1
 BZ_DIRS_EXPLICIT, BZ_DIRS_ICOSA6, BZ_DIRS_PRODUCT, BZ_DIRS_SPIRAL, BZ_DIRS_CIRCLE, BZ_DIRS_DESIGN = 0, 1, 2, 3, 4, 5
-BZ_XF_AUTO, BZ_XF_FUSED, BZ_XF_PLAIN = 0, 1, 2
+BZ_XF_AUTO, BZ_XF_FUSED, BZ_XF_PLAIN, BZ_XF_DFT_GEMM = 0, 1, 2, 3
 BZ_SCATTER = 1
 BZ_CELL_SOLID, BZ_CELL_FORCE_BOLTZMANN = 1, 2
 BZ_REGIME_SOLID = 255

@@ -3,7 +3,8 @@
 For each case (n, m, precision, cells) every strategy the library offers is
 timed on the GPU (HIP events around bz_collide_batch, the plan's own timing):
 the chunked plain pencil passes with 2, 4 or 8 directions per stage-A launch,
-and the fused kernel (FP32, n in {16, 24, 32}) with 1, 2, 4 or 8 direction
+the same passes with the last transforms as DFT matrix products on the matrix
+cores (FP32, n in {16, 32, 48}), and the fused kernel (FP32, n in {16, 24, 32}) with 1, 2, 4 or 8 direction
 chunks per cell and, for n = 16, one or two LDS slices.  A strategy is kept
 only if its output agrees with the plain FP64 path on the same batch
 (relative L2 over the batch <= 2e-5 in FP32, <= 1e-12 in FP64); the fastest
@@ -26,8 +27,13 @@ import paper_2505_03360_amd as bz
 FUSED_SLICES = {16: (1, 2), 24: (1,), 32: (2,)}
 
 
+GEMM_N = (16, 32, 48)
+
+
 def candidates(n: int, m: int, precision: int):
     out = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
+    if precision == bz.BZ_FP32 and n in GEMM_N:
+        out += [(bz.BZ_XF_DFT_GEMM, k, 0) for k in (2, 4, 8)]
     if precision == bz.BZ_FP32 and n in FUSED_SLICES:
         for s in FUSED_SLICES[n]:
             for c in (1, 2, 4, 8):

@@ -83,6 +83,7 @@ struct bz_plan {
   std::vector<double> pscale;   // [m1] per-pass balance factor of the packed transform
   double ginv[25] = {};         // (C C^T)^-1 of the five invariants (dim = 2: 4x4 of four)
   size_t table_mult_bytes = 0, table_w_off = 0, tables_bytes = 0;
+  size_t table_dft_off = 0;     // DFT-as-GEMM plans: matrix-core fragments of the inverse DFT
   size_t ws_fixed = 0, ws_per_cell = 0;
   // binding
   void* tables_dev = nullptr;
@@ -123,6 +124,7 @@ int rule_degree(const std::vector<double>& d, const std::vector<double>& w);
 Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
 bool fused_supported(int n, int fp32);
+bool dft_gemm_supported(int n, int fp32);
 bool fused_slices_supported(int n, int slices);
 int fused_default_chunks(int n, int max_cells);
 // evaluation strategy a three-dimensional descriptor resolves to at a capacity (plan.cpp)

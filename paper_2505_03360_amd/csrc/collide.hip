@@ -81,6 +81,7 @@ struct PlainArgs {
   int first;  // the chunk starting at pass 0 (initialises the accumulator)
   int chunk;  // directions per chunk (stage-A volumes per cell in y)
   int m1;     // passes (directions + the loss pass)
+  const float* dft;  // DFT-as-GEMM plans: matrix-core operand fragments of the inverse DFT
 };
 
 // ------------------------------------------------------------------ forward
@@ -381,6 +382,112 @@ __global__ __launch_bounds__(256, 2) void k_pBC(PlainArgs<T> a) {
   }
 #pragma unroll
   for (int j1 = 0; j1 < N; ++j1) acc[size_t(j1) * N + k] = accr[j1];
+}
+
+// DFT as a matrix product on the matrix cores (BZ_XF_DFT_GEMM plans, FP32):
+// k_pBC with stage C (the length-N inverse transforms along k1 of every j3
+// plane) evaluated as Y = W X by v_mfma_f32_16x16x4_f32, W[j1][k1] =
+// exp(+2 pi i j1 k1 / N).  Complex arithmetic in real form: K = 2N rows
+// [Re X; Im X], Re Y = [Re W | -Im W] [Re X; Im X] and Im Y = [Im W | Re W] [Re
+// X; Im X].  Operand layouts of the 16x16x4 instruction (64 lanes, l): A[i][k]
+// with i = l % 16, k = l / 16; B[k][j] with j = l % 16, k = l / 16; D[i][j]
+// with j = l % 16, i = 4 (l / 16) + r in result register r.  The A operands
+// come from a fragment table in the plan's tables, [Re/Im part][row tile mt]
+// [k step ks][lane], so each is one coalesced load; the B operands are the
+// stage-B outputs in LDS.  A wave owns (plane, column tile) tasks and keeps
+// their products accumulated in registers in D layout: (j1, j2) = (16 mt +
+// 4 (l / 16) + r, 16 nt + l % 16).  The matrix product executes 8N flop per
+// point against the FFT's 5 log2 N.
+template <int N>
+__global__ __launch_bounds__(256, 2) void k_pBC_mm(PlainArgs<float> a) {
+  constexpr int PW = plain_planes_per_group<N>();
+  constexpr int NG = N / PW;
+  constexpr int NT = N / 16, MT = N / 16, KS = N / 2;
+  constexpr int NW = PW * N / 64;              // waves per workgroup
+  constexpr int TPW = PW * NT / NW;            // (plane, column tile) tasks per wave
+  static_assert(N % 16 == 0 && (PW * N) % 64 == 0 && (PW * NT) % NW == 0, "whole tiles and waves");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ cx<float> tr[PW][N][N + 1];  // [plane][j2][k1], odd pitch
+  const int c = blockIdx.x / NG, grp = blockIdx.x % NG;
+  if (c >= live_count(a.ncells, a.ncells_dev)) return;
+  const int t = threadIdx.x;
+  const int pl = t / N, k = t % N;  // stage B: plane, k1
+  const int w = t / 64, l = t % 64;
+  float* acc = a.acc + c * a.acc_stride;
+  float accr[TPW][MT][4];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int tk = w + i * NW, q = tk / NT, nt = tk % NT;
+    const int j3 = grp * PW + q, j2 = 16 * nt + l % 16;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        accr[i][mt][r] = !a.first ? acc[size_t(j3) * N * N + size_t(16 * mt + 4 * (l / 16) + r) * N + j2] : 0.0f;
+  }
+  const long row = a.idx ? long(a.idx[c]) : long(c);
+#pragma unroll 1
+  for (int d = 0; d < a.chunk; ++d) {
+    const int p = a.pass + d;
+    if (p >= a.m1) break;
+    const float wp = a.w[p];
+    {
+      const int j3 = grp * PW + pl;
+      const gptr<cx<float>> y = opaque_global(a.y + c * a.y_stride + size_t(d) * N * N * N + size_t(j3) * N * N + k);
+      cx<float> x[N];
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) x[k2] = y[k2 * N];
+      bzk::fft<N, 1>(x);
+#pragma unroll
+      for (int j2 = 0; j2 < N; ++j2) tr[pl][j2][k] = x[j2];
+    }
+    __syncthreads();
+    const gptr<float> fr = opaque_global(a.dft + l);
+#pragma unroll 1
+    for (int i = 0; i < TPW; ++i) {
+      const int tk = w + i * NW, q = tk / NT, nt = tk % NT;
+      const int j3 = grp * PW + q, j2 = 16 * nt + l % 16;
+      float b[KS];  // rows 4 ks + l / 16 of [Re X; Im X] in column j2
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + l / 16;
+        b[ks] = (4 * ks < N) ? tr[q][j2][kk].x : tr[q][j2][kk - N].y;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f4 dr = {0.0f, 0.0f, 0.0f, 0.0f}, di = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const float ar = fr[((0 * MT + mt) * KS + ks) * 64];
+          const float ai = fr[((1 * MT + mt) * KS + ks) * 64];
+          dr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b[ks], dr, 0, 0, 0);
+          di = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b[ks], di, 0, 0, 0);
+        }
+        if (p == a.m1 - 1) {
+          // loss pass: acc -= (sL f - Im) Re with the exact input f at (j1, j2, j3)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const size_t e = size_t(row) * N * N * N + size_t(16 * mt + 4 * (l / 16) + r) * N * N + size_t(j2) * N + j3;
+            const float fv = a.f_fp32 ? static_cast<const float*>(a.f)[e] : float(static_cast<const double*>(a.f)[e]);
+            accr[i][mt][r] -= (wp * fv - di[r]) * dr[r];
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accr[i][mt][r] += wp * dr[r] * di[r];
+        }
+      }
+    }
+    __syncthreads();  // tr is rewritten by the next direction
+  }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int tk = w + i * NW, q = tk / NT, nt = tk % NT;
+    const int j3 = grp * PW + q, j2 = 16 * nt + l % 16;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[size_t(j3) * N * N + size_t(16 * mt + 4 * (l / 16) + r) * N + j2] = accr[i][mt][r];
+  }
 }
 
 // ------------------------------------------------------------------ fused FP32
@@ -1103,6 +1210,12 @@ void launch_plain_dirs(PlainArgs<T> a, int ncells, int m1, hipStream_t s) {
     a.pass = p0;
     a.first = p0 == 0;
     hipLaunchKernelGGL((k_pA<T, N>), grid, block, 0, s, a);
+    if constexpr (sizeof(T) == 4 && N % 16 == 0) {
+      if (a.dft) {
+        hipLaunchKernelGGL((k_pBC_mm<N>), grid_bc, block_bc, 0, s, a);
+        continue;
+      }
+    }
     hipLaunchKernelGGL((k_pBC<T, N>), grid_bc, block_bc, 0, s, a);
   }
 }
@@ -1256,6 +1369,8 @@ void launch_clear_status(void* ws, const WsLayout& lay, hipStream_t s) {
 
 bool fused_supported(int n, int fp32) { return fp32 && (n == 16 || n == 24 || n == 32); }
 
+bool dft_gemm_supported(int n, int fp32) { return fp32 && (n == 16 || n == 32 || n == 48); }
+
 bool fused_slices_supported(int n, int slices) {
   return (n == 16 && (slices == 1 || slices == 2)) || (n == 24 && slices == 1) || (n == 32 && slices == 2);
 }
@@ -1334,6 +1449,8 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
     a.acc_stride = lay.acc_cell / sizeof(float);
     a.mult = static_cast<const cx<float>*>(b.tables);
     a.w = reinterpret_cast<const float*>(static_cast<const char*>(b.tables) + p->table_w_off);
+    if (p->transform == BZ_XF_DFT_GEMM)
+      a.dft = reinterpret_cast<const float*>(static_cast<const char*>(b.tables) + p->table_dft_off);
     if (p->transform == BZ_XF_FUSED) {
       FwdArgs fw{};
       fw.ncells = ncells;
@@ -1406,7 +1523,7 @@ bz_status launch_collide(const bz_plan* p, const Binding& b, const void* f, int 
   }
   if (st != BZ_OK) return st;
   if (timed) (void)hipEventRecord(pm->ev[2], s);
-  if (!fused_projection && !launch_project(p->n, p->transform == BZ_XF_PLAIN, pa, ncells, s))
+  if (!fused_projection && !launch_project(p->n, p->transform != BZ_XF_FUSED, pa, ncells, s))
     return fail(BZ_ERR_UNSUPPORTED, "projection: n=%d", p->n);
   if (timed) {
     (void)hipEventRecord(pm->ev[3], s);

@@ -351,6 +351,9 @@ void layout2d(bz_plan* p) {
   p->table_mult_bytes = align256(size_t(p->m1) * p->npts * 2 * es);
   p->table_w_off = p->table_mult_bytes;
   p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
+  p->table_dft_off = p->tables_bytes;
+  if (p->transform == BZ_XF_DFT_GEMM)  // [Re/Im part][N/16 row tiles][N/2 k steps][64 lanes] floats
+    p->tables_bytes += align256(size_t(2) * (p->n / 16) * (p->n / 2) * 64 * sizeof(float));
   p->ws = WsLayout{};
   p->ws.fh_cell = spectrum2d_in_workspace(p->n) ? align256(p->npts * 2 * es) : 256;  // the cell's spectrum, [k2][k1]
   p->ws_fixed = kStatusBytes;
@@ -481,23 +484,26 @@ Strategy resolve_strategy(const bz_plan_desc& d, int max_cells, size_t ws_budget
   Strategy sg;
   const int fp32 = d.precision == BZ_FP32;
   const bool fused_ok = fused_supported(d.n, fp32);
+  const bool gemm_ok = dft_gemm_supported(d.n, fp32);
   int transform = d.transform, chunks = d.chunks, slices = d.slices;
   if (transform == BZ_XF_AUTO && chunks == 0 && slices == 0) {
     const TuneChoice tc = tune_lookup(d.n, d.m, d.precision, max_cells);
-    if (tc.found && (tc.transform == BZ_XF_PLAIN || (fused_ok && fused_slices_supported(d.n, tc.slices)))) {
+    if (tc.found && (tc.transform == BZ_XF_PLAIN || (tc.transform == BZ_XF_DFT_GEMM && gemm_ok) ||
+                     (tc.transform == BZ_XF_FUSED && fused_ok && fused_slices_supported(d.n, tc.slices)))) {
       transform = tc.transform;
       chunks = tc.chunks;
       slices = tc.slices;
     }
   }
-  sg.transform = (transform == BZ_XF_PLAIN || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
-  sg.plain_k = (sg.transform == BZ_XF_PLAIN && chunks > 0) ? std::min(chunks, kPlainChunkMax)
+  if (transform == BZ_XF_DFT_GEMM && gemm_ok) sg.transform = BZ_XF_DFT_GEMM;
+  else sg.transform = (transform == BZ_XF_PLAIN || transform == BZ_XF_DFT_GEMM || !fused_ok) ? BZ_XF_PLAIN : BZ_XF_FUSED;
+  sg.plain_k = (sg.transform != BZ_XF_FUSED && chunks > 0) ? std::min(chunks, kPlainChunkMax)
                                                            : plain_chunk(d.n, fp32 != 0, max_cells);
   sg.chunks = sg.transform == BZ_XF_FUSED ? (chunks > 0 ? chunks : fused_default_chunks(d.n, max_cells)) : 1;
   if (sg.chunks > d.m + 1) sg.chunks = d.m + 1;
   sg.slices = slices > 0 ? slices : (d.n == 24 ? 1 : 2);
   // fewer stage-A volumes per cell when the workspace of max_cells cells would exceed the budget
-  if (sg.transform == BZ_XF_PLAIN && !d.dealias)
+  if (sg.transform != BZ_XF_FUSED && !d.dealias)
     while (sg.plain_k > 1 && plain_ws_per_cell(d.n, fp32 != 0, sg.plain_k) * size_t(std::max(1, max_cells)) > ws_budget)
       sg.plain_k /= 2;
   return sg;
@@ -511,6 +517,9 @@ void layout(bz_plan* p) {
   p->table_mult_bytes = align256(size_t(p->m1) * n3 * 2 * es);
   p->table_w_off = p->table_mult_bytes;
   p->tables_bytes = p->table_mult_bytes + align256(size_t(p->m1) * es);
+  p->table_dft_off = p->tables_bytes;
+  if (p->transform == BZ_XF_DFT_GEMM)  // [Re/Im part][N/16 row tiles][N/2 k steps][64 lanes] floats
+    p->tables_bytes += align256(size_t(2) * (p->n / 16) * (p->n / 2) * 64 * sizeof(float));
   // fused: the forward transform keeps its intermediate volumes on chip (no y),
   // and with one chunk and the projection on, the products never leave the chip (no acc)
   const bool fused = p->transform == BZ_XF_FUSED;
@@ -578,6 +587,23 @@ bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
     }
     float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
     for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
+    if (p->transform == BZ_XF_DFT_GEMM) {
+      // A operands of Re Y = [Re W | -Im W] [Re X; Im X] and Im Y = [Im W | Re W] [Re X; Im X],
+      // W[j1][k1] = exp(+2 pi i j1 k1 / n), in the lane order of the 16x16x4 matrix instruction
+      const int n = p->n, mtiles = n / 16, ksteps = n / 2;
+      float* fr = reinterpret_cast<float*>(host.data() + p->table_dft_off);
+      for (int part = 0; part < 2; ++part)
+        for (int mt = 0; mt < mtiles; ++mt)
+          for (int ks = 0; ks < ksteps; ++ks)
+            for (int l = 0; l < 64; ++l) {
+              const int j1 = 16 * mt + l % 16, kk = 4 * ks + l / 16;
+              const int k1 = kk < n ? kk : kk - n;
+              const double ang = 2.0 * kPi * double((j1 * k1) % n) / double(n);
+              const double c = std::cos(ang), sn = std::sin(ang);
+              const double v = part == 0 ? (kk < n ? c : -sn) : (kk < n ? sn : c);
+              fr[((size_t(part) * mtiles + mt) * ksteps + ks) * 64 + l] = float(v);
+            }
+    }
   } else {
     double* m = reinterpret_cast<double*>(host.data());
     for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
@@ -630,7 +656,7 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   if (!(d.kernel_c > 0.0) || !std::isfinite(d.kernel_c)) return fail(BZ_ERR_ARG, "bz_plan_create: kernel_c must be > 0");
   if (d.m < 1 || d.m > 512) return fail(BZ_ERR_ARG, "bz_plan_create: m=%d not in 1..512", d.m);
   if (d.precision != BZ_FP32 && d.precision != BZ_FP64) return fail(BZ_ERR_ARG, "bz_plan_create: bad precision");
-  if (d.transform < BZ_XF_AUTO || d.transform > BZ_XF_PLAIN) return fail(BZ_ERR_ARG, "bz_plan_create: bad transform");
+  if (d.transform < BZ_XF_AUTO || d.transform > BZ_XF_DFT_GEMM) return fail(BZ_ERR_ARG, "bz_plan_create: bad transform");
   if (d.max_cells < 1) return fail(BZ_ERR_ARG, "bz_plan_create: max_cells must be >= 1");
   if (d.chunks < 0 || d.chunks > d.m + 1) return fail(BZ_ERR_ARG, "bz_plan_create: chunks must be in 0..m+1");
   if (d.slices < 0 || d.slices > 2) return fail(BZ_ERR_ARG, "bz_plan_create: slices must be 0, 1 or 2");
@@ -691,13 +717,18 @@ bz_status bz_plan_create(const bz_plan_desc* desc, bz_plan** out) {
   if (!(std::fabs(wsum - 2.0 * kPi) <= 1e-12)) { delete p; return fail(BZ_ERR_ARG, "bz_plan_create: weights sum to %.17g, not 2*pi", wsum); }
 
   const bool fused_ok = fused_supported(p->n, p->fp32);
+  if (d.transform == BZ_XF_DFT_GEMM && !dft_gemm_supported(p->n, p->fp32)) {
+    delete p;
+    return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no DFT-as-GEMM stage for n=%d precision=%s (FP32, n in 16, 32, 48)",
+                d.n, p->fp32 ? "fp32" : "fp64");
+  }
   if (d.transform == BZ_XF_FUSED && !fused_ok) {
     delete p;
     return fail(BZ_ERR_UNSUPPORTED, "bz_plan_create: no fused kernel for n=%d precision=%s", d.n, p->fp32 ? "fp32" : "fp64");
   }
   const Strategy sg = resolve_strategy(d, d.max_cells);
   p->transform = sg.transform;
-  p->plain_k = sg.transform == BZ_XF_PLAIN ? sg.plain_k : 0;
+  p->plain_k = sg.transform != BZ_XF_FUSED ? sg.plain_k : 0;
   p->chunks = sg.chunks;
   p->slices = sg.slices;
   if (p->transform == BZ_XF_FUSED && !fused_slices_supported(p->n, p->slices)) {
@@ -824,7 +855,7 @@ bz_status bz_plan_strategy(const bz_plan* p, int32_t* transform, int32_t* chunks
   clear_error();
   if (!p) return fail(BZ_ERR_ARG, "bz_plan_strategy: null plan");
   if (transform) *transform = p->transform;
-  if (chunks) *chunks = p->transform == BZ_XF_PLAIN ? p->pchunk : p->chunks;
+  if (chunks) *chunks = p->transform != BZ_XF_FUSED ? p->pchunk : p->chunks;
   if (slices) *slices = p->slices;
   return BZ_OK;
 }

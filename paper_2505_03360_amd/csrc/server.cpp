@@ -281,8 +281,8 @@ void builder(bz_server* s) {
     d.max_cells = cp->max_cells;
     if (d.dim != 2 && !d.dealias) {  // the strategy of the key, as explicit knobs
       d.transform = cp->key.sg.transform;
-      d.chunks = cp->key.sg.transform == BZ_XF_PLAIN ? cp->key.sg.plain_k : cp->key.sg.chunks;
-      d.slices = cp->key.sg.transform == BZ_XF_PLAIN ? 0 : cp->key.sg.slices;
+      d.chunks = cp->key.sg.transform != BZ_XF_FUSED ? cp->key.sg.plain_k : cp->key.sg.chunks;
+      d.slices = cp->key.sg.transform != BZ_XF_FUSED ? 0 : cp->key.sg.slices;
     }
     if (d.dir_kind == BZ_DIRS_EXPLICIT) {
       d.dirs = cp->key.dirs.data();

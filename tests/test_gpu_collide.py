@@ -157,6 +157,35 @@ def test_radix3_sizes(n, precision, tol, transform):
     assert err.max() <= tol, err
 
 
+@pytest.mark.parametrize("n,rule,m,cells", [(16, "icosa6", 6, 5), (32, "design", 32, 3), (48, "spiral", 8, 2)])
+def test_dft_gemm_against_oracle(n, rule, m, cells):
+    """BZ_XF_DFT_GEMM plans (the chunked plain path with the transforms along
+    k1 as FP32 MFMA products with the DFT matrix), gathered and scattered
+    rows, against the oracle to the FP32 bound; the FFT plain path on the same
+    cells agrees to the same bound; conservation after projection."""
+    import paper_2505_03360_amd as bz
+    from tests.gpu_util import oracle_plan_of
+    label("dft gemm", n, rule, m)
+    rows = cells + 4
+    allf = gen.shock_batch(rows, n, 8.0, seed=60 + n)
+    idx = np.arange(rows - 1, rows - 1 - 2 * cells, -2).astype(np.int32)
+    col = collider(n, cells, 1, rule=rule, m=m, transform=bz.BZ_XF_DFT_GEMM, chunks=4)
+    assert bz.bz_plan_strategy(col.plan)[:2] == (bz.BZ_XF_DFT_GEMM, 4)
+    out = torch.full((rows, n, n, n), 5.0, dtype=torch.float64, device="cuda")
+    q = run(col, allf, idx=idx, scatter=True, out=out)
+    oplan = oracle_plan_of(col.plan, n, m) if rule == "design" else oracle_plan(n, rule=rule, m=m)
+    ref, loss = oracle_cells(allf[idx], oplan)
+    err = cell_errors(q[idx], ref, loss)
+    print("max err", err.max(), flush=True)
+    assert err.max() <= 1e-5, err
+    assert np.all(q[np.setdiff1d(np.arange(rows), idx)] == 5.0)
+    for c in idx:
+        assert spectral.moment_drift(q[c], n, 8.0) <= 1e-12
+    plain = collider(n, cells, 1, rule=rule, m=m, transform=bz.BZ_XF_PLAIN, chunks=4)
+    qp = run(plain, allf[idx])
+    assert cell_errors(qp, ref, loss).max() <= 1e-5
+
+
 def test_n24_fused_batch_sampled():
     """N=24 on the fused kernel (one cell per workgroup, the whole 24^3 volume
     in LDS, planes that straddle waves): 300 shock cells with the spherical

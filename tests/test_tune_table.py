@@ -1,4 +1,6 @@
 """The tune table steers bz_plan_create (host only, no GPU needed)."""
+import pytest
+
 import paper_2505_03360_amd as bz
 from paper_2505_03360_amd.autotune import candidates, write_table
 
@@ -75,8 +77,31 @@ def test_shipped_table_is_read_by_default():
 
 def test_candidate_set():
     plain = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
+    gemm = [(bz.BZ_XF_DFT_GEMM, k, 0) for k in (2, 4, 8)]
     c16 = candidates(16, 32, bz.BZ_FP32)
-    assert c16[:3] == plain and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 11
+    assert c16[:6] == plain + gemm and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 14
     assert candidates(24, 32, bz.BZ_FP32) == plain + [(bz.BZ_XF_FUSED, c, 1) for c in (1, 2, 4, 8)]
-    assert candidates(48, 32, bz.BZ_FP32) == plain
+    assert candidates(48, 32, bz.BZ_FP32) == plain + gemm
     assert candidates(32, 32, bz.BZ_FP64) == plain
+
+
+def test_dft_gemm_plans():
+    """BZ_XF_DFT_GEMM: FP32 plans at n in {16, 32, 48}; the plan's tables grow
+    by the matrix-core operand fragments of the inverse DFT."""
+    for n in (16, 32, 48):
+        p = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=16,
+                                                transform=bz.BZ_XF_DFT_GEMM, chunks=4))
+        q = bz.bz_plan_create(bz.make_plan_desc(n=n, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=16,
+                                                transform=bz.BZ_XF_PLAIN, chunks=4))
+        try:
+            assert bz.bz_plan_strategy(p)[:2] == (bz.BZ_XF_DFT_GEMM, 4)
+            tp, fp, pp = bz.bz_plan_device_bytes(p)
+            tq, fq, pq = bz.bz_plan_device_bytes(q)
+            assert tp - tq == -(-2 * (n // 16) * (n // 2) * 64 * 4 // 256) * 256 and (fp, pp) == (fq, pq)
+        finally:
+            bz.bz_plan_destroy(p)
+            bz.bz_plan_destroy(q)
+    for kw in (dict(n=24), dict(n=32, precision=bz.BZ_FP64)):
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_plan_create(bz.make_plan_desc(m=8, dir_kind=bz.BZ_DIRS_SPIRAL, transform=bz.BZ_XF_DFT_GEMM, **kw))
+        assert e.value.code == bz.BZ_ERR_UNSUPPORTED
