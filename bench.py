@@ -250,7 +250,7 @@ def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
         # mean cells per request of the clipped Poisson(512) draw
         mean_cells = float(np.clip(np.random.default_rng(seed).poisson(512, 200000), 16, 4096).mean())
         rate = 0.8 * rec["cells_per_s"] / mean_cells  # requests per second over the 4 clients
-        olat, ocells, ofailed, orejected = [], [0], [0], [0]
+        olat, ocells, ofailed, orejected, ophase = [], [0], [0], [0], []
 
         def open_client(cid):
             rng = np.random.default_rng(seed * 1000 + cid)
@@ -269,6 +269,7 @@ def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
                     with lock:
                         if r.state == bz.BZ_REQ_DONE:
                             olat.append(((r.t_done_ns - r.t_submit_ns) * 1e-6, q.shape[-1]))
+                            ophase.append(((r.t_admit_ns - r.t_submit_ns) * 1e-6, (r.t_done_ns - r.t_admit_ns) * 1e-6))
                             ocells[0] += kk
                         else:
                             ofailed[0] += 1
@@ -302,7 +303,13 @@ def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
         odt = time.perf_counter() - t0
         oby_n = per_class(olat)
         olat = np.array([x for x, _ in olat])
+        ph = np.array(ophase)
         rec["open_loop"] = {"by_n": oby_n,
+                            "admit_wait_ms": {"p50": float(np.percentile(ph[:, 0], 50)),
+                                              "p99": float(np.percentile(ph[:, 0], 99))},
+                            "admitted_to_done_ms": {"p50": float(np.percentile(ph[:, 1], 50)),
+                                                    "p99": float(np.percentile(ph[:, 1], 99))},
+                            "max_ms": float(olat.max()),
             "offered_requests_per_s": rate, "offered_cells_per_s": rate * mean_cells,
             "requests": int(olat.size), "failed": ofailed[0], "rejected": orejected[0],
             "p50_ms": float(np.percentile(olat, 50)), "p99_ms": float(np.percentile(olat, 99)),
@@ -603,6 +610,7 @@ def main():
     ap.add_argument("--serve-open-requests", type=int, default=300,
                     help="open-loop serving requests per client at 80%% of capacity (0 = skip)")
     ap.add_argument("--sweep", action="store_true", help="run the precision sweep instead (one JSON line per case)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving workload (one JSON line)")
     ap.add_argument("--sweep-n", type=int, nargs="*", default=[32, 48])
     ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
     ap.add_argument("--sweep-gamma", type=float, nargs="*", default=[0.0, 0.5, 1.0])
@@ -623,6 +631,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:
         sweep(ns=args.sweep_n, ms=args.sweep_m, gammas=args.sweep_gamma, cpu=not args.no_cpu)
+        return
+    if args.serving_only:
+        print(json.dumps(serving_run(args.serve_seconds, open_requests=args.serve_open_requests)))
         return
     f_np = gen.shock_batch(CELLS, N, L, seed=2)
     f = torch.from_numpy(f_np).cuda()

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define BZ_ABI_VERSION 4
+#define BZ_ABI_VERSION 5
 
 typedef int32_t bz_status;
 
@@ -484,7 +484,11 @@ bz_status bz_mask_sync(const int32_t* counts, void* stream);
  * admitted in arrival order as soon as their workspace fits in the arena and
  * an in-flight slot is free (a request that does not fit may be passed by at
  * most 8 later ones); admitted requests run on n_streams streams, so their
- * work overlaps on the device.  Plans are cached by descriptor (max_cells is
+ * work overlaps on the device, and a request larger than the slice size runs
+ * as consecutive slices, each launched when the previous one has finished on
+ * the stream with the least estimated work queued (cells x grid points x
+ * passes), so long requests interleave with short ones.
+ * The strategy of a request's plan is that of its slice size.  Plans are cached by descriptor (max_cells is
  * ignored): the host plan is built on a builder thread the first time an
  * operator is requested (meanwhile its requests wait and the others go
  * ahead), its device tables are uploaded into the arena when a request needs
@@ -508,6 +512,10 @@ typedef struct {
   int32_t max_inflight; /* requests on the GPU at once (>= 1) */
   int32_t n_streams;    /* launch streams (1..16), default priority */
   int32_t max_queue;    /* queued requests before bz_serve_submit returns BZ_AGAIN */
+  int32_t slice_cells;  /* cells per launch; larger requests run slice by slice, one
+                           slice in flight at a time on the least loaded stream, with
+                           a workspace of one slice; 0 = by grid size (n = 16: 4096,
+                           24: 2048, 32: 1024, 48: 512; two dimensions: 8192) */
 } bz_server_desc;
 
 typedef struct {

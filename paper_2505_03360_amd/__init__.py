@@ -64,7 +64,8 @@ class BzMaskDesc(ctypes.Structure):
 
 class BzServerDesc(ctypes.Structure):
     _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
-                ("max_inflight", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+                ("max_inflight", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("slice_cells", ctypes.c_int32)]
 
 
 class BzRequest(ctypes.Structure):
@@ -116,7 +117,7 @@ class BzError(RuntimeError):
 
 
 _LIB = None
-ABI_VERSION = 4  # the struct layouts below match include/bz.h at this version
+ABI_VERSION = 5  # the struct layouts below match include/bz.h at this version
 
 # (name, restype, argtypes) for every symbol declared in include/bz.h
 _VP = ctypes.c_void_p
@@ -637,12 +638,13 @@ class Server:
     """A serving runtime whose arena is one torch uint8 tensor."""
 
     def __init__(self, arena_bytes: int, max_inflight: int = 8, n_streams: int = 4, max_queue: int = 4096,
-                 device="cuda"):
+                 device="cuda", slice_cells: int = 0):
         torch = _torch()
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
         d = BzServerDesc()
         d.arena_dev, d.arena_bytes = _ptr(self.arena), arena_bytes
         d.max_inflight, d.n_streams, d.max_queue = max_inflight, n_streams, max_queue
+        d.slice_cells = slice_cells
         torch.cuda.synchronize()
         self.handle = bz_server_create(d)
         self._keep = {}
@@ -650,12 +652,22 @@ class Server:
     def submit(self, f, q, plan: BzPlanDesc, idx=None, ncells=None, scatter=False, client_id=0):
         torch = _torch()
         n3 = plan.n ** (2 if plan.dim == 2 else 3)
+        rows_f = f.numel() // n3
+        k = ncells if ncells is not None else (idx.numel() if idx is not None else rows_f)
+        # the server reads and writes exactly the rows the request names: check the buffers hold them
+        if (idx is None and k > rows_f) or (idx is not None and (idx.numel() < k or idx.dtype != torch.int32)):
+            raise ValueError(f"request names {k} cells, f holds {rows_f} rows and idx {None if idx is None else idx.numel()}")
+        out_dtype = torch.float64 if plan.project or plan.precision == BZ_FP64 else torch.float32
+        if q.dtype != out_dtype or not q.is_contiguous() or not f.is_contiguous():
+            raise ValueError(f"f must be contiguous and q a contiguous {out_dtype} tensor")
+        if q.numel() // n3 < (rows_f if scatter else k):
+            raise ValueError(f"q holds {q.numel() // n3} rows, the request writes up to row {(rows_f if scatter else k) - 1}")
         r = BzRequest()
         r.plan = plan
         r.f = _ptr(f)
         r.f_dtype = BZ_FP32 if f.dtype == torch.float32 else BZ_FP64
         r.idx = _ptr(idx)
-        r.ncells = ncells if ncells is not None else (idx.numel() if idx is not None else f.numel() // n3)
+        r.ncells = k
         r.q = _ptr(q)
         r.flags = BZ_SCATTER if scatter else 0
         r.client_id = client_id

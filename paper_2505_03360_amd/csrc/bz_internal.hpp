@@ -123,6 +123,7 @@ int rule_degree(const std::vector<double>& d, const std::vector<double>& w);
 // plan helpers (plan.cpp)
 Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_bytes);
 bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s);
+void fill_tables_host(const bz_plan* p, unsigned char* host);  // the device image of the tables (tables_bytes)
 bool fused_supported(int n, int fp32);
 bool dft_gemm_supported(int n, int fp32);
 bool fused_slices_supported(int n, int slices);

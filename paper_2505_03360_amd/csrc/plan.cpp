@@ -572,26 +572,29 @@ Binding make_binding(const bz_plan* p, const void* tables, void* ws, size_t ws_b
   return b;
 }
 
-bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
-  if (p->pad) return upload_tables(p->pad, tables_dev, s);
+void fill_tables_host(const bz_plan* p, unsigned char* host) {
+  if (p->pad) {
+    fill_tables_host(p->pad, host);
+    return;
+  }
   const size_t n3 = p->npts;
-  std::vector<unsigned char> host(p->tables_bytes, 0);
+  std::memset(host, 0, p->tables_bytes);
   const size_t entries = size_t(p->m1) * n3;
   if (p->fp32) {
-    float* m = reinterpret_cast<float*>(host.data());
+    float* m = reinterpret_cast<float*>(host);
     for (size_t e = 0; e < entries; ++e) {
       double re, im;
       device_multiplier(p, int(e / n3), e % n3, re, im);
       m[2 * e] = float(re);
       m[2 * e + 1] = float(im);
     }
-    float* w = reinterpret_cast<float*>(host.data() + p->table_w_off);
+    float* w = reinterpret_cast<float*>(host + p->table_w_off);
     for (int i = 0; i < p->m1; ++i) w[i] = float(p->wext[i]);
     if (p->transform == BZ_XF_DFT_GEMM) {
       // A operands of Re Y = [Re W | -Im W] [Re X; Im X] and Im Y = [Im W | Re W] [Re X; Im X],
       // W[j1][k1] = exp(+2 pi i j1 k1 / n), in the lane order of the 16x16x4 matrix instruction
       const int n = p->n, mtiles = n / 16, ksteps = n / 2;
-      float* fr = reinterpret_cast<float*>(host.data() + p->table_dft_off);
+      float* fr = reinterpret_cast<float*>(host + p->table_dft_off);
       for (int part = 0; part < 2; ++part)
         for (int mt = 0; mt < mtiles; ++mt)
           for (int ks = 0; ks < ksteps; ++ks)
@@ -605,10 +608,15 @@ bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
             }
     }
   } else {
-    double* m = reinterpret_cast<double*>(host.data());
+    double* m = reinterpret_cast<double*>(host);
     for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
-    std::memcpy(host.data() + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
+    std::memcpy(host + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
   }
+}
+
+bz_status upload_tables(const bz_plan* p, void* tables_dev, hipStream_t s) {
+  std::vector<unsigned char> host(p->tables_bytes);
+  fill_tables_host(p, host.data());
   hipError_t e = hipMemcpyAsync(tables_dev, host.data(), p->tables_bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(BZ_ERR_DEVICE, "table upload failed: %s", hipGetErrorString(e));

@@ -135,12 +135,29 @@ PlanKey make_key(const bz_plan_desc& d, int ncells, size_t arena_bytes) {
 enum { kPlanBuilding = 0, kPlanReady = 1, kPlanFailed = 2 };
 
 // Host plans built once per operator; device tables present while `resident`.
+// Cells per launch: a request larger than this is evaluated in slices, one in
+// flight at a time, each on the least loaded stream, so that a long request
+// holds a stream for one slice (a few ms) instead of its whole run and shorter
+// requests interleave with it; the workspace holds one slice.
+int slice_cells(const bz_server_desc& d, const bz_plan_desc& pd) {
+  if (d.slice_cells > 0) return d.slice_cells;
+  if (pd.dim == 2) return 8192;
+  switch (pd.n) {
+    case 16: return 4096;
+    case 24: return 2048;
+    case 32: return 1024;
+    default: return 512;
+  }
+}
+
 struct CachedPlan {
   PlanKey key;
   int max_cells = 1;      // capacity the host plan is built for (its strategy follows from it)
   int state = kPlanBuilding;
   bz_status err = BZ_OK;  // build error (kPlanFailed)
   bz_plan* plan = nullptr;
+  unsigned char* image = nullptr;  // pinned host copy of the device tables (built with the plan)
+  hipEvent_t uploaded = nullptr;   // completion of the last upload of the image into the arena
   bool resident = false;
   size_t tables_off = 0, tables_bytes = 0;
   int inflight = 0;
@@ -161,7 +178,15 @@ struct Req {
   size_t ws_off = 0, ws_bytes = 0;
   hipEvent_t ev = nullptr;
   int slot = -1;  // pinned host word that receives the request's numeric status
+  int slice = 0;  // cells per launch (the request is evaluated slice by slice)
+  int done_cells = 0;  // cells whose slice has been launched
+  int stream = -1;     // stream of the slice in flight (-1: admitted, waiting for its next slice)
+  double work = 0.0;   // estimated work of the slice in flight
 };
+
+// Slices queued per stream at most: the server, not the streams' FIFO order,
+// decides which request runs next.
+constexpr int kStreamDepth = 2;
 
 }  // namespace
 
@@ -170,6 +195,8 @@ struct bz_server {
   Arena arena;
   int device = 0;
   std::vector<hipStream_t> streams;
+  std::vector<double> stream_load;  // estimated work of the slices in flight per stream
+  std::vector<int> stream_depth;    // slices in flight per stream
   hipStream_t upload = nullptr;
   std::vector<hipEvent_t> event_pool;
   int32_t* status_host = nullptr;  // pinned, one word per in-flight slot
@@ -184,7 +211,6 @@ struct bz_server {
   std::condition_variable build_cv;
   uint64_t gen = 0;  // bumped by every event the scheduler may wait for (submit, build done, stop)
   uint64_t next_ticket = 1;
-  int next_stream = 0;
   bool stop = false;          // drain and stop the scheduler
   bool builder_stop = false;  // set once the scheduler has drained
   std::thread th, builder;
@@ -221,6 +247,23 @@ hipEvent_t take_event(bz_server* s) {
   return e;
 }
 
+// Release a resident plan's table region (after its upload has landed).
+void drop_tables(bz_server* s, CachedPlan* c) {
+  if (c->uploaded) (void)hipEventSynchronize(c->uploaded);
+  s->arena.release(c->tables_off, c->tables_bytes);
+  c->resident = false;
+}
+
+void free_plan(CachedPlan* c) {
+  if (c->uploaded) (void)hipEventSynchronize(c->uploaded);
+  if (c->plan) bz_plan_destroy(c->plan);
+  if (c->image) (void)hipHostFree(c->image);
+  if (c->uploaded) (void)hipEventDestroy(c->uploaded);
+  c->plan = nullptr;
+  c->image = nullptr;
+  c->uploaded = nullptr;
+}
+
 // Drop the device tables of idle resident plans (least recently used first)
 // until `need` bytes can be allocated or nothing idle is left; their host
 // plans stay cached.
@@ -230,8 +273,7 @@ bool alloc_with_eviction(bz_server* s, size_t need, size_t* off) {
     for (auto& c : s->plans)
       if (c->resident && c->inflight == 0 && (!victim || c->last_use < victim->last_use)) victim = c.get();
     if (!victim) return false;
-    s->arena.release(victim->tables_off, victim->tables_bytes);
-    victim->resident = false;
+    drop_tables(s, victim);
   }
   return true;
 }
@@ -249,7 +291,7 @@ void trim_host_plans(bz_server* s) {
     bool queued = false;  // requests still name it: keep it
     for (uint64_t id : s->queue) queued |= s->reqs[id].cp == s->plans[vi].get();
     if (queued) return;
-    if (s->plans[vi]->plan) bz_plan_destroy(s->plans[vi]->plan);
+    free_plan(s->plans[vi].get());
     s->plans.erase(s->plans.begin() + long(vi));
   }
 }
@@ -261,7 +303,7 @@ CachedPlan* find_plan(bz_server* s, Req& q) {
     if (c->key == q.key) return c.get();
   auto c = std::make_unique<CachedPlan>();
   c->key = q.key;
-  c->max_cells = std::max(1, q.r.ncells);
+  c->max_cells = std::max(1, std::min(q.r.ncells, q.slice));
   s->plans.push_back(std::move(c));
   CachedPlan* cp = s->plans.back().get();
   s->build_q.push_back(cp);
@@ -290,9 +332,22 @@ void builder(bz_server* s) {
     }
     lk.unlock();
     bz_plan* p = nullptr;
-    const bz_status st = bz_plan_create(&d, &p);
+    bz_status st = bz_plan_create(&d, &p);
+    unsigned char* image = nullptr;
+    hipEvent_t ev = nullptr;
+    if (st == BZ_OK) {
+      // the device image of the tables, pinned so that uploads are asynchronous copies
+      if (hipHostMalloc(reinterpret_cast<void**>(&image), p->tables_bytes, hipHostMallocDefault) != hipSuccess ||
+          hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        st = bz::fail(BZ_ERR_DEVICE, "server: pinned table image");
+      } else {
+        bz::fill_tables_host(p, image);
+      }
+    }
     lk.lock();
     cp->plan = p;
+    cp->image = image;
+    cp->uploaded = ev;
     cp->err = st;
     cp->state = st == BZ_OK ? kPlanReady : kPlanFailed;
     if (st == BZ_OK) cp->tables_bytes = p->tables_bytes;
@@ -306,37 +361,139 @@ void builder(bz_server* s) {
 bool make_resident(bz_server* s, CachedPlan* cp, bz_status* err) {
   if (cp->resident) return true;
   if (!alloc_with_eviction(s, cp->tables_bytes, &cp->tables_off)) return false;
-  const bz_status up = bz::upload_tables(cp->plan, s->arena.base + cp->tables_off, s->upload);
-  if (up != BZ_OK) {
+  // asynchronous copy from the pinned image; the request's kernels wait for the event
+  if (hipMemcpyAsync(s->arena.base + cp->tables_off, cp->image, cp->tables_bytes, hipMemcpyHostToDevice,
+                     s->upload) != hipSuccess ||
+      hipEventRecord(cp->uploaded, s->upload) != hipSuccess) {
+    (void)hipStreamSynchronize(s->upload);
     s->arena.release(cp->tables_off, cp->tables_bytes);
-    *err = up;
+    *err = BZ_ERR_DEVICE;
     return false;
   }
   cp->resident = true;
   return true;
 }
 
+// Launch the request's next slice on the least loaded stream (the first one
+// after its ready event, with its status word cleared); the status word goes
+// to the request's pinned host slot after the last slice.
+bz_status launch_slice(bz_server* s, Req& q, int st_i) {
+  hipStream_t st = s->streams[size_t(st_i)];
+  const bz_plan* p = q.cp->plan;
+  const bz::Binding b = bz::make_binding(p, s->arena.base + q.cp->tables_off, s->arena.base + q.ws_off, q.ws_bytes);
+  const bool first = q.done_cells == 0;
+  if (first && q.r.ready_event && hipStreamWaitEvent(st, static_cast<hipEvent_t>(q.r.ready_event), 0) != hipSuccess)
+    return BZ_ERR_DEVICE;
+  if (first && hipStreamWaitEvent(st, q.cp->uploaded, 0) != hipSuccess) return BZ_ERR_DEVICE;  // the tables
+  if (first) bz::launch_clear_status(b.ws, b.lay, st);
+  const int cnt = std::min(q.slice, q.r.ncells - q.done_cells);
+  if (cnt > 0) {
+    const size_t npts = p->npts;
+    const char* f = static_cast<const char*>(q.r.f);
+    const int32_t* idx = q.r.idx;
+    if (idx) idx += q.done_cells;
+    else f += size_t(q.done_cells) * npts * (q.r.f_dtype == BZ_FP32 ? 4 : 8);
+    char* out = static_cast<char*>(q.r.q);
+    const bool scatter = (q.r.flags & BZ_SCATTER) != 0;
+    if (!scatter) out += size_t(q.done_cells) * npts * ((p->project || !p->fp32) ? 8 : 4);
+    const bz_status lst = bz::launch_collide(p, b, f, q.r.f_dtype == BZ_FP32, idx, cnt, nullptr, out, scatter, st, false);
+    if (lst != BZ_OK) return lst;
+  }
+  q.done_cells += cnt;
+  if (q.done_cells >= q.r.ncells &&
+      hipMemcpyAsync(&s->status_host[q.slot], static_cast<char*>(b.ws) + b.lay.status_off, sizeof(int32_t),
+                     hipMemcpyDeviceToHost, st) != hipSuccess)
+    return BZ_ERR_DEVICE;
+  if (hipEventRecord(q.ev, st) != hipSuccess) return BZ_ERR_DEVICE;
+  q.stream = st_i;
+  q.work = double(std::max(cnt, 1)) * double(p->npts) * double(p->m1);  // cells x grid points x passes
+  s->stream_load[size_t(st_i)] += q.work;
+  s->stream_depth[size_t(st_i)] += 1;
+  return BZ_OK;
+}
+
+// Estimated work left of an admitted request (cells x grid points x passes).
+double remaining_work(const Req& q) {
+  return double(std::max(q.r.ncells - q.done_cells, 1)) * double(q.cp->plan->npts) * double(q.cp->plan->m1);
+}
+
+// End an admitted request: free its workspace, slot and event.
+void retire(bz_server* s, size_t i, int state, bz_status err) {
+  Req& q = s->reqs[s->inflight[i]];
+  s->arena.release(q.ws_off, q.ws_bytes);
+  q.cp->inflight -= 1;
+  if (q.ev) s->event_pool.push_back(q.ev);
+  q.ev = nullptr;
+  if (q.slot >= 0) s->free_slots.push_back(q.slot);
+  q.slot = -1;
+  finish(s, q, state, err);
+  s->inflight[i] = s->inflight.back();
+  s->inflight.pop_back();
+  s->gen += 1;
+}
+
+// Launch slices while a stream has room (fewer than kStreamDepth queued): the
+// waiting request with the least work left goes first, on the stream with the
+// fewest (then the lightest) slices queued, so short requests overtake long
+// ones at slice boundaries.
+void dispatch(bz_server* s) {
+  for (;;) {
+    int st_i = 0;
+    for (int i = 1; i < int(s->streams.size()); ++i) {
+      const size_t a = size_t(i), b = size_t(st_i);
+      if (s->stream_depth[a] < s->stream_depth[b] ||
+          (s->stream_depth[a] == s->stream_depth[b] && s->stream_load[a] < s->stream_load[b]))
+        st_i = i;
+    }
+    if (s->stream_depth[size_t(st_i)] >= kStreamDepth) return;
+    size_t best = s->inflight.size();
+    double best_work = 0.0;
+    for (size_t i = 0; i < s->inflight.size(); ++i) {
+      const Req& q = s->reqs[s->inflight[i]];
+      if (q.stream >= 0) continue;
+      const double w = remaining_work(q);
+      if (best == s->inflight.size() || w < best_work) {
+        best = i;
+        best_work = w;
+      }
+    }
+    if (best == s->inflight.size()) return;
+    Req& q = s->reqs[s->inflight[best]];
+    const bz_status lst = launch_slice(s, q, st_i);
+    if (lst != BZ_OK) {
+      for (auto x : s->streams) (void)hipStreamSynchronize(x);  // nothing of a failed launch stays in flight
+      if (q.stream >= 0) {
+        s->stream_load[size_t(q.stream)] -= q.work;
+        s->stream_depth[size_t(q.stream)] -= 1;
+      }
+      retire(s, best, BZ_REQ_FAILED, lst);
+    }
+  }
+}
+
 void reap(bz_server* s) {
   for (size_t i = 0; i < s->inflight.size();) {
     Req& q = s->reqs[s->inflight[i]];
+    if (q.stream < 0) {  // waiting for its next slice
+      ++i;
+      continue;
+    }
     const hipError_t e = hipEventQuery(q.ev);
     if (e == hipErrorNotReady) {
       ++i;
       continue;
     }
-    s->arena.release(q.ws_off, q.ws_bytes);
-    q.cp->inflight -= 1;
-    s->event_pool.push_back(q.ev);
-    q.ev = nullptr;
+    s->stream_load[size_t(q.stream)] -= q.work;
+    s->stream_depth[size_t(q.stream)] -= 1;
+    q.stream = -1;
+    if (e == hipSuccess && q.done_cells < q.r.ncells) {  // the next slice waits for dispatch
+      ++i;
+      continue;
+    }
     const bool nonfinite = q.slot >= 0 && s->status_host[q.slot] != 0;
-    if (q.slot >= 0) s->free_slots.push_back(q.slot);
-    q.slot = -1;
-    if (e != hipSuccess) finish(s, q, BZ_REQ_FAILED, BZ_ERR_DEVICE);
-    else if (nonfinite) finish(s, q, BZ_REQ_FAILED, BZ_ERR_NUMERIC);
-    else finish(s, q, BZ_REQ_DONE, BZ_OK);
-    s->inflight[i] = s->inflight.back();
-    s->inflight.pop_back();
-    s->gen += 1;
+    if (e != hipSuccess) retire(s, i, BZ_REQ_FAILED, BZ_ERR_DEVICE);
+    else if (nonfinite) retire(s, i, BZ_REQ_FAILED, BZ_ERR_NUMERIC);
+    else retire(s, i, BZ_REQ_DONE, BZ_OK);
   }
 }
 
@@ -348,10 +505,7 @@ bool place(bz_server* s, CachedPlan* cp, size_t ws, size_t* off, bz_status* err)
   cp->inflight += 1;  // pin the plan while allocating
   bool ok = make_resident(s, cp, err) && alloc_with_eviction(s, ws, off);
   if (!ok && *err == BZ_OK && s->inflight.empty()) {
-    if (cp->resident) {
-      s->arena.release(cp->tables_off, cp->tables_bytes);
-      cp->resident = false;
-    }
+    if (cp->resident) drop_tables(s, cp);
     ok = alloc_with_eviction(s, ws, off);
     if (ok && !make_resident(s, cp, err)) {
       s->arena.release(*off, ws);
@@ -384,7 +538,7 @@ bool admit(bz_server* s) {
       continue;
     }
     const bz_plan* p = cp->plan;
-    const size_t ws = p->ws_fixed + p->ws_per_cell * size_t(std::max(1, q.r.ncells));
+    const size_t ws = p->ws_fixed + p->ws_per_cell * size_t(std::max(1, std::min(q.r.ncells, q.slice)));
     if (bz::align256(ws) + bz::align256(cp->tables_bytes) > s->arena.bytes) {  // can never fit
       finish(s, q, BZ_REQ_FAILED, BZ_ERR_NOMEM);
       s->queue.erase(s->queue.begin() + long(qi));
@@ -407,41 +561,24 @@ bool admit(bz_server* s) {
       continue;
     }
     hipEvent_t ev = take_event(s);
-    hipStream_t st = s->streams[size_t(s->next_stream)];
-    s->next_stream = (s->next_stream + 1) % int(s->streams.size());
-    const bz::Binding b = bz::make_binding(p, s->arena.base + cp->tables_off, s->arena.base + off, ws);
-    bz_status lst = ev ? BZ_OK : BZ_ERR_DEVICE;
+    s->queue.erase(s->queue.begin() + long(qi));
+    progress = true;
+    if (!ev) {
+      s->arena.release(off, ws);
+      finish(s, q, BZ_REQ_FAILED, BZ_ERR_DEVICE);
+      continue;
+    }
     const int slot = s->free_slots.back();  // at most max_inflight requests are in flight
     s->free_slots.pop_back();
     s->status_host[slot] = 0;
-    if (lst == BZ_OK && q.r.ready_event &&
-        hipStreamWaitEvent(st, static_cast<hipEvent_t>(q.r.ready_event), 0) != hipSuccess)
-      lst = BZ_ERR_DEVICE;
-    if (lst == BZ_OK && q.r.ncells > 0) {
-      bz::launch_clear_status(b.ws, b.lay, st);
-      lst = bz::launch_collide(p, b, q.r.f, q.r.f_dtype == BZ_FP32, q.r.idx, q.r.ncells, nullptr, q.r.q,
-                               (q.r.flags & BZ_SCATTER) != 0, st, false);
-      if (lst == BZ_OK &&
-          hipMemcpyAsync(&s->status_host[slot], static_cast<char*>(b.ws) + b.lay.status_off, sizeof(int32_t),
-                         hipMemcpyDeviceToHost, st) != hipSuccess)
-        lst = BZ_ERR_DEVICE;
-    }
-    if (lst == BZ_OK && hipEventRecord(ev, st) != hipSuccess) lst = BZ_ERR_DEVICE;
-    s->queue.erase(s->queue.begin() + long(qi));
-    progress = true;
-    if (lst != BZ_OK) {
-      s->arena.release(off, ws);
-      if (ev) s->event_pool.push_back(ev);
-      s->free_slots.push_back(slot);
-      finish(s, q, BZ_REQ_FAILED, lst);
-      continue;
-    }
     q.slot = slot;
-    q.state = BZ_REQ_ADMITTED;
-    q.t_admit = now_ns();
     q.ws_off = off;
     q.ws_bytes = ws;
     q.ev = ev;
+    q.done_cells = 0;
+    q.stream = -1;  // its first slice waits for dispatch
+    q.state = BZ_REQ_ADMITTED;
+    q.t_admit = now_ns();
     cp->inflight += 1;
     cp->last_use = q.t_admit;
     s->inflight.push_back(id);
@@ -456,6 +593,7 @@ void scheduler(bz_server* s) {
     reap(s);
     const uint64_t seen = s->gen;
     admit(s);
+    dispatch(s);
     trim_host_plans(s);
     if (s->stop && s->queue.empty() && s->inflight.empty()) break;
     if (s->inflight.empty()) {
@@ -480,8 +618,9 @@ bz_status bz_server_create(const bz_server_desc* d, bz_server** out) {
   *out = nullptr;
   if (!d->arena_dev || d->arena_bytes < kAlign) return bz::fail(BZ_ERR_ARG, "bz_server_create: arena missing or too small");
   if (uintptr_t(d->arena_dev) & (kAlign - 1)) return bz::fail(BZ_ERR_ARG, "bz_server_create: arena must be 256-byte aligned");
-  if (d->max_inflight < 1 || d->n_streams < 1 || d->n_streams > 16 || d->max_queue < 1)
-    return bz::fail(BZ_ERR_ARG, "bz_server_create: need max_inflight >= 1, 1 <= n_streams <= 16, max_queue >= 1");
+  if (d->max_inflight < 1 || d->n_streams < 1 || d->n_streams > 16 || d->max_queue < 1 || d->slice_cells < 0)
+    return bz::fail(BZ_ERR_ARG, "bz_server_create: need max_inflight >= 1, 1 <= n_streams <= 16, max_queue >= 1, "
+                    "slice_cells >= 0");
   auto s = std::make_unique<bz_server>();
   s->d = *d;
   s->arena.init(d->arena_dev, d->arena_bytes);
@@ -496,6 +635,8 @@ bz_status bz_server_create(const bz_server_desc* d, bz_server** out) {
     if (i < d->n_streams) s->streams.push_back(st);
     else s->upload = st;
   }
+  s->stream_load.assign(s->streams.size(), 0.0);
+  s->stream_depth.assign(s->streams.size(), 0);
   if (hipHostMalloc(reinterpret_cast<void**>(&s->status_host), sizeof(int32_t) * size_t(d->max_inflight),
                     hipHostMallocDefault) != hipSuccess) {
     for (auto x : s->streams) (void)hipStreamDestroy(x);
@@ -525,7 +666,8 @@ bz_status bz_serve_submit(bz_server* s, const bz_request* r, uint64_t* ticket) {
   Req q;
   q.ticket = s->next_ticket++;
   q.r = *r;
-  q.key = make_key(r->plan, r->ncells, s->arena.bytes);
+  q.slice = slice_cells(s->d, r->plan);
+  q.key = make_key(r->plan, std::min(r->ncells, q.slice), s->arena.bytes);
   q.t_submit = now_ns();
   if (s->submitted == 0) s->t_first_submit = q.t_submit;
   s->submitted += 1;
@@ -610,8 +752,7 @@ bz_status bz_server_destroy(bz_server* s) {
   }
   s->build_cv.notify_all();
   if (s->builder.joinable()) s->builder.join();
-  for (auto& c : s->plans)
-    if (c->plan) bz_plan_destroy(c->plan);
+  for (auto& c : s->plans) free_plan(c.get());
   for (auto e : s->event_pool) (void)hipEventDestroy(e);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
   if (s->upload) (void)hipStreamDestroy(s->upload);

@@ -142,13 +142,15 @@ def test_admission_bounded_by_arena():
 def test_failed_requests_are_isolated():
     import paper_2505_03360_amd as bz
     print("case serve failures", flush=True)
-    srv = bz.Server(arena_bytes=512 << 20, max_inflight=4, n_streams=2)
+    # an arena of 128 MB: one 4096-cell slice of an N = 16 request needs ~200 MB of workspace
+    srv = bz.Server(arena_bytes=128 << 20, max_inflight=4, n_streams=2)
     f = inputs(16, 4, 8)
     good = torch.empty((4, 16, 16, 16), dtype=torch.float64, device="cuda")
     bad_n = bz.make_plan_desc(n=20, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL)
     t_bad = srv.submit(f, good, bad_n)
-    huge = torch.empty(1, dtype=torch.float64, device="cuda")
-    t_huge = srv.submit(f, huge, plan(bz, 16), ncells=400000)  # can never fit the arena
+    big_f = torch.zeros((4096, 16, 16, 16), dtype=torch.float64, device="cuda")  # valid buffers, never read
+    big_q = torch.empty_like(big_f)
+    t_huge = srv.submit(big_f, big_q, plan(bz, 16))  # its slice can never fit the arena
     t_good = srv.submit(f, good, plan(bz, 16))
     r_bad, r_huge, r_good = wait(srv, t_bad), wait(srv, t_huge), wait(srv, t_good)
     assert r_bad.state == bz.BZ_REQ_FAILED and r_bad.err == bz.BZ_ERR_UNSUPPORTED
@@ -156,6 +158,8 @@ def test_failed_requests_are_isolated():
     assert r_good.state == bz.BZ_REQ_DONE
     with pytest.raises(bz.BzError):
         srv.poll(t_good)  # already collected
+    with pytest.raises(ValueError):  # buffers smaller than the cells named: refused by the binding
+        srv.submit(f, good, plan(bz, 16), ncells=400000)
     st = srv.stats()
     assert st.failed == 2 and st.completed == 1
     srv.close()
@@ -246,4 +250,45 @@ def test_request_waits_for_pending_input_writes():
     torch.cuda.synchronize()
     assert wait(srv, srv.submit(src, q_ref, pd)).state == bz.BZ_REQ_DONE
     assert torch.equal(q, q_ref)
+    srv.close()
+
+
+def test_sliced_requests_match_direct_slices():
+    """With slice_cells = 16, requests of 40 cells run as slices of 16, 16 and
+    8 cells (one at a time, on the least loaded stream): the result equals a
+    direct bz_collide_batch of each slice with a plan of that size, compact
+    and scattered, alone and beside other requests; one cell against the
+    oracle."""
+    import paper_2505_03360_amd as bz
+    print("case serve sliced", flush=True)
+    n, c = 16, 40
+    srv = bz.Server(arena_bytes=1 << 30, max_inflight=6, n_streams=3, slice_cells=16)
+    f = inputs(n, 2 * c, 51)
+    col = bz.Collider(n, 16, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, precision=1)
+    direct = torch.cat([col(f[a:b]) for a, b in ((0, 16), (16, 32), (32, 40))])
+    idx = torch.arange(2 * c - 1, 0, -2, dtype=torch.int32, device="cuda")  # rows 79, 77, ..., 1
+    dsc = torch.zeros((2 * c, n, n, n), dtype=torch.float64, device="cuda")
+    for a, b in ((0, 16), (16, 32), (32, 40)):
+        col(f, idx=idx[a:b].contiguous(), out=dsc, scatter=True)
+    q = torch.empty((c, n, n, n), dtype=torch.float64, device="cuda")
+    assert wait(srv, srv.submit(f[:c], q, plan(bz, n))).state == bz.BZ_REQ_DONE
+    assert torch.equal(q, direct)
+    qs = torch.zeros_like(dsc)
+    assert wait(srv, srv.submit(f, qs, plan(bz, n), idx=idx, scatter=True)).state == bz.BZ_REQ_DONE
+    assert torch.equal(qs, dsc)
+    # in a mix with small requests of other sizes
+    small = inputs(24, 5, 52)
+    outs = []
+    tickets = []
+    for r in range(3):
+        qq = torch.empty_like(q)
+        qsm = torch.empty((5, 24, 24, 24), dtype=torch.float64, device="cuda")
+        tickets.append(srv.submit(f[:c], qq, plan(bz, n), client_id=r))
+        tickets.append(srv.submit(small, qsm, plan(bz, 24), client_id=r))
+        outs.append(qq)
+    for t in tickets:
+        assert wait(srv, t).state == bz.BZ_REQ_DONE
+    for qq in outs:
+        assert torch.equal(qq, direct)
+    OracleCells().check("sliced", f[:c], q, 37)
     srv.close()
