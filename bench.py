@@ -388,7 +388,7 @@ def sweep(cells: int = 1024, reps: int = 3, ns=(32, 48), ms=(32, 64), gammas=(0.
     return out
 
 
-def loss_norms(f, plan: int, n: int = N, kernel_c: float = 4.0):
+def loss_norms(f, plan: int, n: int = N, kernel_c: float = 4.0, m: int = M):
     """Per cell ||C fN Lambda||_2, the loss term of the operator (fN the
     truncated series of f, Lambda = IDFT(Bhat_M fhat)), for the floor of the
     per-cell error measure; evaluated with torch FFTs on the GPU from the
@@ -397,7 +397,6 @@ def loss_norms(f, plan: int, n: int = N, kernel_c: float = 4.0):
     import torch
 
     import paper_2505_03360_amd as bz
-    m = bz.bz_plan_get_rule(plan, M)[1].size
     bh = torch.from_numpy(bz.bz_plan_get_multipliers(plan, n, m)[0]).cuda()
     nyq = torch.zeros((n, n, n), dtype=torch.bool, device="cuda")
     nyq[n // 2] = nyq[:, n // 2] = nyq[:, :, n // 2] = True
@@ -409,6 +408,80 @@ def loss_norms(f, plan: int, n: int = N, kernel_c: float = 4.0):
         lam = torch.fft.ifftn(fh * bh, dim=(1, 2, 3)).real
         out[c0:c0 + 32] = kernel_c * torch.linalg.vector_norm((fn * lam).reshape(fn.shape[0], -1), dim=1)
     return out
+
+
+def single_cell_latency(reps: int = 50):
+    """The single-cell workload: one cell, N = 16, M = 6 (icosahedral axes),
+    hard spheres, a seeded mix of two Maxwellians; wall time of one
+    bz_collide_batch call including the launch, host to completion, FP64 and
+    FP32 plans (median of `reps` calls after warm-up)."""
+    import numpy as np
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    f = torch.from_numpy(gen.bimaxwellian_batch(1, 16, L, seed=1)).cuda()
+    out = {}
+    for name, prec in (("fp64", bz.BZ_FP64), ("fp32", bz.BZ_FP32)):
+        col = bz.Collider(16, 1, L=L, m=6, dir_kind=bz.BZ_DIRS_ICOSA6, precision=prec)
+        q = col(f)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            col(f, out=q)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        out[f"{name}_ms"] = float(np.median(ts))
+        out[f"{name}_strategy"] = list(bz.bz_plan_strategy(col.plan))
+        col.close()
+    out["workload"] = "1 cell, N=16^3 on [-8,8]^3, M=6 icosahedral axes, hard spheres, two-Maxwellian mix, " \
+                      "host wall time per call (launch to completion), median of %d" % reps
+    return out
+
+
+def compact_sweep(cells: int = 1024, reps: int = 3):
+    """The precision sweep at gamma = 1 (hard spheres): N in {32, 48}, M in
+    {32, 64}, FP32 (with FP64 projection) and FP64 plans on the same 1024
+    shock cells, time per batch and the FP32 error against FP64 (per cell with
+    the near-equilibrium floor of the loss term)."""
+    import torch
+
+    import bz_inputs as gen
+    import paper_2505_03360_amd as bz
+
+    rows = []
+    for n in (32, 48):
+        f = torch.from_numpy(gen.shock_batch(64, n, L, seed=4)).cuda().repeat(cells // 64, 1, 1, 1).contiguous()
+        for m in (32, 64):
+            res, ms = {}, {}
+            for name, prec in (("fp32", bz.BZ_FP32), ("fp64", bz.BZ_FP64)):
+                col = bz.Collider(n, cells, L=L, m=m, dir_kind=bz.BZ_DIRS_DESIGN, precision=prec)
+                q = col(f)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    col(f, out=q)
+                torch.cuda.synchronize()
+                ms[name] = 1e3 * (time.perf_counter() - t0) / reps
+                res[name] = q
+                if name == "fp32":
+                    plan32 = col
+                else:
+                    col.close()
+            d = (res["fp32"] - res["fp64"]).reshape(cells, -1)
+            rn = torch.linalg.vector_norm(res["fp64"].reshape(cells, -1), dim=1)
+            floor = 0.05 * loss_norms(f, plan32.plan, n=n, m=m)
+            err = torch.linalg.vector_norm(d, dim=1) / torch.maximum(rn, floor)
+            plan32.close()
+            rows.append({"n": n, "m": m, "cells": cells, "fp32_ms": ms["fp32"], "fp64_ms": ms["fp64"],
+                         "fp32_cells_per_s": cells / (ms["fp32"] * 1e-3),
+                         "fp32_vs_fp64_max_cell_floored": float(err.max()),
+                         "fp32_vs_fp64_batch": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(res["fp64"]))})
+            del res
+            torch.cuda.empty_cache()
+    return rows
 
 
 def kinetic_run(col, f, steps: int):
@@ -611,6 +684,7 @@ def main():
                     help="open-loop serving requests per client at 80%% of capacity (0 = skip)")
     ap.add_argument("--sweep", action="store_true", help="run the precision sweep instead (one JSON line per case)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload (one JSON line)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the compact precision sweep leg")
     ap.add_argument("--sweep-n", type=int, nargs="*", default=[32, 48])
     ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
     ap.add_argument("--sweep-gamma", type=float, nargs="*", default=[0.0, 0.5, 1.0])
@@ -723,12 +797,16 @@ def main():
                                            "cells against the FP64 GPU path; cancellation cells: the floor binds"},
         "algorithmic_tflops_whole_step": total_flops * value / 1e12,
     }
+    rec["single_cell"] = single_cell_latency()
     rec["kinetic"] = kinetic_run(col, f, max(2, args.steps // 2))
     rec["dealiased"] = dealias_run(f, out, max(2, args.steps // 4))
     rec["maxwell2d"] = maxwell2d_run(max(2, args.steps // 4))
     rec["graph_step"] = graph_step_run(f)
-    if args.serve_seconds > 0:
+    if not args.no_sweep:
         del out64, col64
+        torch.cuda.empty_cache()
+        rec["sweep"] = compact_sweep()
+    if args.serve_seconds > 0:
         torch.cuda.empty_cache()
         rec["serving"] = serving_run(args.serve_seconds, open_requests=args.serve_open_requests)
         ol = rec["serving"].get("open_loop")
