@@ -112,7 +112,7 @@ typedef struct {
                             the plain path's directions per chunk at n = 48
                             (FP32: 8 up to 1024 cells, else 4; results do not
                             depend on it) */
-  int32_t chunks;        /* plain path: directions per stage-A launch (1..8; 0 =
+  int32_t chunks;        /* plain path: directions per stage-A launch (1..17; 0 =
                             from max_cells, as described under max_cells);
                             fused path: direction chunks per cell, each a workgroup;
                             0 = from max_cells (n = 24, 32: 4 up to 64 cells, 2 up

@@ -2,7 +2,8 @@
 
 For each case (n, m, precision, cells) every strategy the library offers is
 timed on the GPU (HIP events around bz_collide_batch, the plan's own timing):
-the chunked plain pencil passes with 2, 4 or 8 directions per stage-A launch,
+the chunked plain pencil passes with 2, 4, 8 or (up to 17) a third or half of the
+passes per stage-A launch,
 the same passes with the last transforms as DFT matrix products on the matrix
 cores (FP32, n in {16, 32, 48}), and the fused kernel (FP32, n in {16, 24, 32}) with 1, 2, 4 or 8 direction
 chunks per cell and, for n = 16, one or two LDS slices.  A strategy is kept
@@ -30,8 +31,15 @@ FUSED_SLICES = {16: (1, 2), 24: (1,), 32: (2,)}
 GEMM_N = (16, 32, 48)
 
 
+def plain_ks(m: int):
+    """Directions per stage-A launch tried for the plain path: 2, 4, 8 and the
+    sizes that split the m + 1 passes into three or two equal launch pairs."""
+    m1 = m + 1
+    return sorted({2, 4, 8} | {k for k in (-(-m1 // 3), -(-m1 // 2)) if 8 < k <= 17})
+
+
 def candidates(n: int, m: int, precision: int):
-    out = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
+    out = [(bz.BZ_XF_PLAIN, k, 0) for k in plain_ks(m)]
     if precision == bz.BZ_FP32 and n in GEMM_N:
         out += [(bz.BZ_XF_DFT_GEMM, k, 0) for k in (2, 4, 8)]
     if precision == bz.BZ_FP32 and n in FUSED_SLICES:

@@ -30,7 +30,7 @@ inline int plain_chunk(int n, bool fp32, int max_cells) {
   if (n <= 32) return 8;
   return (fp32 && max_cells <= 1024) ? 8 : 4;
 }
-constexpr int kPlainChunkMax = 8;
+constexpr int kPlainChunkMax = 17;  // 33 passes of a 32-direction plan: two launch pairs
 // Two-dimensional plans keep a cell's spectrum in the workspace from n = 32
 // up (the LDS then holds one transpose buffer per cell: twice the waves per
 // CU); at n = 16 it stays in the LDS, which does not limit occupancy there.

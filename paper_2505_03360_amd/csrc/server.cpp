@@ -114,14 +114,12 @@ PlanKey make_key(const bz_plan_desc& d, int ncells, size_t arena_bytes) {
   k.d = d;
   // a plan picks its strategy from its capacity (tune table or size
   // heuristics; the plain path's stage-A volumes per cell so that the
-  // workspace fits the arena): requests that resolve to different strategies
+  // workspace fits a quarter of the arena): requests that resolve to different strategies
   // get (and cache) different plans, built with that strategy as explicit
   // knobs, so a request's arithmetic depends only on its own size
-  if (d.dim != 2) {
-    const size_t n3 = size_t(d.n) * d.n * d.n, es = d.precision == BZ_FP32 ? 4 : 8;
-    const size_t tables = size_t(std::max(1, d.m) + 1) * n3 * 2 * es + 4096;
-    k.sg = bz::resolve_strategy(d, std::max(1, ncells), arena_bytes > tables ? arena_bytes - tables : 0);
-  }
+  // (a request's workspace is held to a quarter of the arena, so that several
+  // large requests fit at once)
+  if (d.dim != 2) k.sg = bz::resolve_strategy(d, std::max(1, ncells), arena_bytes / 4);
   k.d.max_cells = 0;
   k.d.dirs = nullptr;
   k.d.weights = nullptr;

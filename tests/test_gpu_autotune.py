@@ -18,7 +18,7 @@ def test_autotune_small_case(tmp_path):
     from paper_2505_03360_amd.autotune import tune_case, write_table
     print("case autotune", flush=True)
     best, rows = tune_case(16, 8, bz.BZ_FP32, 6, reps=2)
-    assert len(rows) == 14 and all(r["ok"] for r in rows), rows
+    assert len(rows) == 14 and all(r["ok"] for r in rows), rows  # m = 8: plain k in {2, 4, 8}
     write_table(str(tmp_path / "t.txt"), [(16, 8, bz.BZ_FP32, 6) + best])
     bz.bz_set_tune_table(str(tmp_path / "t.txt"))
     try:

@@ -46,8 +46,8 @@ def test_tune_table_selects_strategy(tmp_path):
 
 
 def test_plain_directions_per_launch_knob():
-    for k in (1, 2, 5, 8):
-        p = bz.bz_plan_create(bz.make_plan_desc(n=48, m=8, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=16, chunks=k,
+    for k in (1, 2, 5, 8, 17):
+        p = bz.bz_plan_create(bz.make_plan_desc(n=48, m=32, dir_kind=bz.BZ_DIRS_SPIRAL, max_cells=16, chunks=k,
                                                 transform=bz.BZ_XF_PLAIN))
         tb, fixed, per = bz.bz_plan_device_bytes(p)
         assert bz.bz_plan_strategy(p)[:2] == (bz.BZ_XF_PLAIN, k)
@@ -76,10 +76,10 @@ def test_shipped_table_is_read_by_default():
 
 
 def test_candidate_set():
-    plain = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8)]
+    plain = [(bz.BZ_XF_PLAIN, k, 0) for k in (2, 4, 8, 11, 17)]
     gemm = [(bz.BZ_XF_DFT_GEMM, k, 0) for k in (2, 4, 8)]
     c16 = candidates(16, 32, bz.BZ_FP32)
-    assert c16[:6] == plain + gemm and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 14
+    assert c16[:8] == plain + gemm and (bz.BZ_XF_FUSED, 8, 1) in c16 and len(c16) == 16
     assert candidates(24, 32, bz.BZ_FP32) == plain + [(bz.BZ_XF_FUSED, c, 1) for c in (1, 2, 4, 8)]
     assert candidates(48, 32, bz.BZ_FP32) == plain + gemm
     assert candidates(32, 32, bz.BZ_FP64) == plain
