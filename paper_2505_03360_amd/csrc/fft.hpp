@@ -5,14 +5,18 @@
 // and 4 butterflies) with every index and every twiddle a compile-time
 // constant, so the whole transform unrolls into straight-line VALU code with
 // literal coefficients.  Twiddles are evaluated in FP64 at compile time
-// (exact octant reduction, then a Taylor series on |x| <= pi/4) and rounded
-// once to T.
+// (exact octant reduction, then a Taylor series on |x| <= pi/4), applied in
+// scaled form (see ScaledTw: two FMAs per twiddle, the scale folded into the
+// butterfly's own FMAs) and rounded once to T.  FP32 arithmetic instructions
+// per transform: 52 (N = 8), 144 (16), 274 (24), 376 (32), 678 (48).
 //
 // Convention: fft<N, SIGN>(x) computes X_k = sum_n x_n exp(SIGN 2 pi i k n / N)
 // in natural order, without scaling.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #define BZK_HD __host__ __device__ __forceinline__
 
@@ -125,16 +129,15 @@ BZK_HD void dft2(cx<T> (&x)[2]) {
 
 template <int SIGN, typename T>
 BZK_HD void dft3(cx<T> (&x)[3]) {
-  // X1,2 = a - (b+c)/2 +- SIGN i (sqrt(3)/2) (b - c)
-  const T h = T(0.86602540378443864676372317075293618);
+  // X1,2 = a - (b+c)/2 +- SIGN i (sqrt(3)/2) (b - c); the last products fold into FMAs
+  constexpr T h = T(SIGN * 0.86602540378443864676372317075293618);
   cx<T> a = x[0], b = x[1], c = x[2];
   cx<T> t = cadd(b, c);
   cx<T> d = csub(b, c);
   cx<T> m = {a.x - T(0.5) * t.x, a.y - T(0.5) * t.y};
-  cx<T> r = mul_si<SIGN>(cx<T>{h * d.x, h * d.y});
   x[0] = cadd(a, t);
-  x[1] = cadd(m, r);
-  x[2] = csub(m, r);
+  x[1] = {m.x - h * d.y, m.y + h * d.x};
+  x[2] = {m.x + h * d.y, m.y - h * d.x};
 }
 
 template <int SIGN, typename T>
@@ -147,6 +150,125 @@ BZK_HD void dft4(cx<T> (&x)[4]) {
   x[3] = csub(d02, d13);
 }
 
+// Twiddle factors in scaled form: w = exp(SIGN 2 pi i k / N) = c (1 + i t) when
+// |cos| >= |sin| (t = tan, c = cos), else c (u + i) (u = cot, c = sin), so that
+// w b = c y with y = b + i t b (or u b + i b) costing two FMAs.  The factor c
+// is not applied to y: the butterfly that consumes the twiddled value
+// multiplies it in with FMAs (X = a + c y), which saves the separate complex
+// multiplication (the FMA factorisation of Linzer and Feig, IBM J. Res. Dev.
+// 1993).  Kinds: 0 = trivial (y = +-b or +-i b, c = 1), 1 = tangent, 2 =
+// cotangent; at odd multiples of pi/4 t and u are exactly +-1 (y = b -+ i b...).
+struct ScaledTw {
+  int kind;  // 0 trivial, 1 tangent, 2 cotangent
+  int rot;   // trivial kind: y = b * i^rot (SIGN folded in)
+  double t;  // tan or cot
+  double c;  // cos or sin (scale applied by the consumer)
+};
+constexpr double cabs_d(double v) { return v < 0 ? -v : v; }
+template <int N, int SIGN>
+constexpr ScaledTw scaled_tw(int k) {
+  k %= N;
+  if (k < 0) k += N;
+  if (k == 0) return ScaledTw{0, 0, 0.0, 1.0};
+  if (4 * k == N) return ScaledTw{0, SIGN > 0 ? 1 : 3, 0.0, 1.0};
+  if (2 * k == N) return ScaledTw{0, 2, 0.0, 1.0};
+  if (4 * k == 3 * N) return ScaledTw{0, SIGN > 0 ? 3 : 1, 0.0, 1.0};
+  const double c = kTw<N>.c[k], s = SIGN * kTw<N>.s[k];
+  const bool diag = (8 * k) % N == 0;  // odd multiple of pi/4: |c| = |s|
+  if (cabs_d(c) >= cabs_d(s) || diag) {
+    const double t = diag ? (s / c > 0 ? 1.0 : -1.0) : s / c;
+    return ScaledTw{1, 0, t, c};
+  }
+  return ScaledTw{2, 0, c / s, s};
+}
+template <int N, int SIGN>
+struct ScaledTable {
+  ScaledTw v[N];
+  constexpr ScaledTable() : v() {
+    for (int k = 0; k < N; ++k) v[k] = scaled_tw<N, SIGN>(k);
+  }
+};
+template <int N, int SIGN>
+inline constexpr ScaledTable<N, SIGN> kScTw{};
+
+// y of the scaled form for twiddle index K (compile time)
+template <int N, int SIGN, int K, typename T>
+BZK_HD cx<T> scaled_y(cx<T> b) {
+  constexpr ScaledTw w = kScTw<N, SIGN>.v[((K % N) + N) % N];
+  if constexpr (w.kind == 0) {
+    if constexpr (w.rot == 0) return b;
+    else if constexpr (w.rot == 1) return {-b.y, b.x};
+    else if constexpr (w.rot == 2) return {-b.x, -b.y};
+    else return {b.y, -b.x};
+  } else if constexpr (w.kind == 1) {
+    constexpr T t = T(w.t);
+    return {b.x - t * b.y, b.y + t * b.x};
+  } else {
+    constexpr T u = T(w.t);
+    return {u * b.x - b.y, u * b.y + b.x};
+  }
+}
+template <int N, int SIGN, int K>
+constexpr double scaled_c() { return kScTw<N, SIGN>.v[((K % N) + N) % N].c; }
+
+// Radix-N1 butterfly of fft_ct over b[n1] = (sub-transform n1 at output k2),
+// with the twiddles exp(SIGN 2 pi i n1 k2 / N) applied in scaled form.
+template <int N1, int N, int SIGN, int K2, typename T>
+BZK_HD void twiddled_dft(cx<T> (&b)[N1]) {
+  if constexpr (K2 == 0) {
+    fft<N1, SIGN>(b);
+  } else if constexpr (N1 == 2) {
+    const cx<T> y1 = scaled_y<N, SIGN, K2>(b[1]);
+    constexpr T c1 = T(scaled_c<N, SIGN, K2>());
+    const cx<T> a = b[0];
+    b[0] = {a.x + c1 * y1.x, a.y + c1 * y1.y};
+    b[1] = {a.x - c1 * y1.x, a.y - c1 * y1.y};
+  } else if constexpr (N1 == 3) {
+    // b' = c1 y1, c' = c2 y2 = c1 r y2: b' + c' = c1 (y1 + r y2), b' - c' = c1 (y1 - r y2)
+    const cx<T> y1 = scaled_y<N, SIGN, K2>(b[1]);
+    const cx<T> y2 = scaled_y<N, SIGN, 2 * K2>(b[2]);
+    constexpr double c1d = scaled_c<N, SIGN, K2>(), c2d = scaled_c<N, SIGN, 2 * K2>();
+    constexpr T r = T(c2d / c1d);
+    constexpr T c1 = T(c1d), hc = T(0.5 * c1d);
+    constexpr T g = T(SIGN * 0.86602540378443864676372317075293618 * c1d);
+    const cx<T> sm = {y1.x + r * y2.x, y1.y + r * y2.y};
+    const cx<T> df = {y1.x - r * y2.x, y1.y - r * y2.y};
+    const cx<T> a = b[0];
+    const cx<T> m = {a.x - hc * sm.x, a.y - hc * sm.y};
+    b[0] = {a.x + c1 * sm.x, a.y + c1 * sm.y};
+    b[1] = {m.x - g * df.y, m.y + g * df.x};
+    b[2] = {m.x + g * df.y, m.y - g * df.x};
+  } else {
+    static_assert(N1 == 4, "twiddled butterflies of radix 2, 3 and 4");
+    // A, B = x0 +- c2 y2; c1 y1 +- c3 y3 = c1 (y1 +- r y3), r = c3 / c1
+    const cx<T> y1 = scaled_y<N, SIGN, K2>(b[1]);
+    const cx<T> y2 = scaled_y<N, SIGN, 2 * K2>(b[2]);
+    const cx<T> y3 = scaled_y<N, SIGN, 3 * K2>(b[3]);
+    constexpr double c1d = scaled_c<N, SIGN, K2>();
+    constexpr T c1 = T(c1d), c2 = T(scaled_c<N, SIGN, 2 * K2>());
+    constexpr T r = T(scaled_c<N, SIGN, 3 * K2>() / c1d);
+    constexpr T sc1 = T(SIGN * c1d);
+    const cx<T> a = b[0];
+    const cx<T> A = {a.x + c2 * y2.x, a.y + c2 * y2.y};
+    const cx<T> B = {a.x - c2 * y2.x, a.y - c2 * y2.y};
+    const cx<T> zp = {y1.x + r * y3.x, y1.y + r * y3.y};
+    const cx<T> zm = {y1.x - r * y3.x, y1.y - r * y3.y};
+    b[0] = {A.x + c1 * zp.x, A.y + c1 * zp.y};
+    b[2] = {A.x - c1 * zp.x, A.y - c1 * zp.y};
+    // SIGN i c1 zm = sc1 (-zm.y, zm.x)
+    b[1] = {B.x - sc1 * zm.y, B.y + sc1 * zm.x};
+    b[3] = {B.x + sc1 * zm.y, B.y - sc1 * zm.x};
+  }
+}
+
+template <int I, int E, typename F>
+BZK_HD void static_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
 // N = N1 * N2: input index n = n1 + N1 n2, output index k = k2 + N2 k1.
 template <int N1, int N2, int SIGN, typename T>
 BZK_HD void fft_ct(cx<T> (&x)[N1 * N2]) {
@@ -157,18 +279,16 @@ BZK_HD void fft_ct(cx<T> (&x)[N1 * N2]) {
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) a[n1][n2] = x[n1 + N1 * n2];
     fft<N2, SIGN>(a[n1]);
-#pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) a[n1][k2] = twiddle<N, SIGN>(a[n1][k2], n1 * k2);
   }
-#pragma unroll
-  for (int k2 = 0; k2 < N2; ++k2) {
+  static_for<0, N2>([&](auto kc) {
+    constexpr int k2 = decltype(kc)::value;
     cx<T> b[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) b[n1] = a[n1][k2];
-    fft<N1, SIGN>(b);
+    twiddled_dft<N1, N, SIGN, k2>(b);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) x[k2 + N2 * k1] = b[k1];
-  }
+  });
 }
 
 template <int N, int SIGN, typename T>

@@ -188,7 +188,13 @@ def test_imex_equilibrium_and_conservation():
     col = bz.Collider(n, 2, L=L, precision=bz.BZ_FP32, m=32, dir_kind=bz.BZ_DIRS_SPIRAL)
     ft = torch.from_numpy(f).cuda()
     out = col.imex_euler(ft, torch.zeros_like(ft), 0.01, eps=1e-3).cpu().numpy()
-    assert np.abs(out[0] - M[0]).max() <= 1e-6 * M.max()
+    # for f = M and no transport eq. (4.24) leaves f^{n+1} - M = dt Q(M) / (eps + beta dt),
+    # beta = 2 pi rho: the FP32 operator's error bar (1e-5 of the loss-floored norm) scaled
+    # by the step's factor bounds the departure from equilibrium
+    qq, _, ql = spectral.collide_parts(M[0], oracle_plan(n, rule="spiral", m=32))
+    factor = 0.01 / (1e-3 + 2.0 * np.pi * 0.01)
+    bound = factor * 1e-5 * max(np.linalg.norm(qq), 0.05 * np.linalg.norm(ql))
+    assert np.linalg.norm(out[0] - M[0]) <= bound
     out = col.imex_euler(ft, torch.from_numpy(tr).cuda(), 0.01, eps=1e-3).cpu().numpy()
     for c in range(2):
         U1 = kinetic.conserved(f[c] - 0.01 * tr[c], n, L)
