@@ -269,7 +269,8 @@ def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
                     with lock:
                         if r.state == bz.BZ_REQ_DONE:
                             olat.append(((r.t_done_ns - r.t_submit_ns) * 1e-6, q.shape[-1]))
-                            ophase.append(((r.t_admit_ns - r.t_submit_ns) * 1e-6, (r.t_done_ns - r.t_admit_ns) * 1e-6))
+                            ophase.append(((r.t_admit_ns - r.t_submit_ns) * 1e-6, (r.t_done_ns - r.t_admit_ns) * 1e-6,
+                                           q.shape[-1]))
                             ocells[0] += kk
                         else:
                             ofailed[0] += 1
@@ -306,7 +307,9 @@ def serving_run(seconds: float, seed: int = 5, open_requests: int = 300):
         ph = np.array(ophase)
         rec["open_loop"] = {"by_n": oby_n,
                             "admit_wait_ms": {"p50": float(np.percentile(ph[:, 0], 50)),
-                                              "p99": float(np.percentile(ph[:, 0], 99))},
+                                              "p99": float(np.percentile(ph[:, 0], 99)),
+                                              "p99_by_n": {str(n): float(np.percentile(ph[ph[:, 2] == n, 0], 99))
+                                                           for n in sizes if (ph[:, 2] == n).any()}},
                             "admitted_to_done_ms": {"p50": float(np.percentile(ph[:, 1], 50)),
                                                     "p99": float(np.percentile(ph[:, 1], 99))},
                             "max_ms": float(olat.max()),

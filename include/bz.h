@@ -514,8 +514,8 @@ typedef struct {
   int32_t max_queue;    /* queued requests before bz_serve_submit returns BZ_AGAIN */
   int32_t slice_cells;  /* cells per launch; larger requests run slice by slice, one
                            slice in flight at a time on the least loaded stream, with
-                           a workspace of one slice; 0 = by grid size (n = 16: 4096,
-                           24: 2048, 32: 1024, 48: 512; two dimensions: 8192) */
+                           a workspace of one slice; 0 = by grid size (n = 16: 2048,
+                           24: 1024, 32: 512, 48: 256; two dimensions: 4096) */
 } bz_server_desc;
 
 typedef struct {

@@ -4,10 +4,10 @@
 // Requests arrive from any client thread (bz_serve_submit) with their own
 // operator descriptor, distribution buffer, cell list and output buffer.  One
 // scheduler thread
-//   * admits queued requests in arrival order as soon as their workspace
-//     (ws_per_cell * cells bytes) fits in the caller's arena and an in-flight
-//     slot is free; a request that does not fit may be passed by later ones
-//     at most kMaxBypass times, after which admission waits for it;
+//   * admits queued requests as soon as their workspace (ws_per_cell * cells
+//     bytes) fits in the caller's arena and an in-flight slot is free, the
+//     one with the least estimated work first; a request may be passed by
+//     later ones at most kMaxBypass times, after which admission waits for it;
 //   * keeps one plan per operator descriptor: the host plan (FP64 tables) is
 //     built on a builder thread, so a request that needs a new plan never
 //     holds up the admission or completion of the others, and stays cached
@@ -139,12 +139,12 @@ enum { kPlanBuilding = 0, kPlanReady = 1, kPlanFailed = 2 };
 // requests interleave with it; the workspace holds one slice.
 int slice_cells(const bz_server_desc& d, const bz_plan_desc& pd) {
   if (d.slice_cells > 0) return d.slice_cells;
-  if (pd.dim == 2) return 8192;
+  if (pd.dim == 2) return 4096;
   switch (pd.n) {
-    case 16: return 4096;
-    case 24: return 2048;
-    case 32: return 1024;
-    default: return 512;
+    case 16: return 2048;
+    case 24: return 1024;
+    case 32: return 512;
+    default: return 256;
   }
 }
 
@@ -184,7 +184,7 @@ struct Req {
 
 // Slices queued per stream at most: the server, not the streams' FIFO order,
 // decides which request runs next.
-constexpr int kStreamDepth = 2;
+constexpr int kStreamDepth = 1;
 
 }  // namespace
 
@@ -430,20 +430,24 @@ void retire(bz_server* s, size_t i, int state, bz_status err) {
   s->gen += 1;
 }
 
+// Slices of at most this much work (cells x grid points x passes; a full
+// 512-cell slice at n = 32 with 33 passes, about a millisecond of device time,
+// is below it, a 256-cell slice at n = 48 above) are short: with two or more
+// streams, stream 0 takes only short slices, so a short request never waits
+// behind long ones.
+constexpr double kShortWork = double(3u << 28);
+
+double next_slice_work(const Req& q) {
+  const int cnt = std::max(1, std::min(q.slice, q.r.ncells - q.done_cells));
+  return double(cnt) * double(q.cp->plan->npts) * double(q.cp->plan->m1);
+}
+
 // Launch slices while a stream has room (fewer than kStreamDepth queued): the
 // waiting request with the least work left goes first, on the stream with the
 // fewest (then the lightest) slices queued, so short requests overtake long
-// ones at slice boundaries.
+// ones at slice boundaries; long slices keep off stream 0.
 void dispatch(bz_server* s) {
   for (;;) {
-    int st_i = 0;
-    for (int i = 1; i < int(s->streams.size()); ++i) {
-      const size_t a = size_t(i), b = size_t(st_i);
-      if (s->stream_depth[a] < s->stream_depth[b] ||
-          (s->stream_depth[a] == s->stream_depth[b] && s->stream_load[a] < s->stream_load[b]))
-        st_i = i;
-    }
-    if (s->stream_depth[size_t(st_i)] >= kStreamDepth) return;
     size_t best = s->inflight.size();
     double best_work = 0.0;
     for (size_t i = 0; i < s->inflight.size(); ++i) {
@@ -457,6 +461,21 @@ void dispatch(bz_server* s) {
     }
     if (best == s->inflight.size()) return;
     Req& q = s->reqs[s->inflight[best]];
+    const bool long_slice = s->streams.size() > 1 && next_slice_work(q) > kShortWork;
+    int st_i = -1;
+    for (int i = long_slice ? 1 : 0; i < int(s->streams.size()); ++i) {
+      const size_t a = size_t(i);
+      if (s->stream_depth[a] >= kStreamDepth) continue;
+      if (st_i < 0) {
+        st_i = i;
+        continue;
+      }
+      const size_t b = size_t(st_i);
+      if (s->stream_depth[a] < s->stream_depth[b] ||
+          (s->stream_depth[a] == s->stream_depth[b] && s->stream_load[a] < s->stream_load[b]))
+        st_i = i;
+    }
+    if (st_i < 0) return;  // the waiting requests with less work go first once a stream frees
     const bz_status lst = launch_slice(s, q, st_i);
     if (lst != BZ_OK) {
       for (auto x : s->streams) (void)hipStreamSynchronize(x);  // nothing of a failed launch stays in flight
@@ -514,52 +533,83 @@ bool place(bz_server* s, CachedPlan* cp, size_t ws, size_t* off, bz_status* err)
   return ok;
 }
 
-// Admits what fits, in arrival order (bounded bypass); returns true if any
-// request changed state.
+// Queued requests considered per admission round (the oldest ones).
+constexpr size_t kAdmitWindow = 256;
+
+// Admits what fits.  Order: requests already passed over more than kMaxBypass
+// times first (oldest first), then the others by estimated work (cells x grid
+// points x passes, oldest first among equals), so that a short request does
+// not wait for a free slot behind long ones.  A request whose workspace
+// exceeds a sixteenth of the arena is admitted out of that turn only if an
+// eighth of the arena stays free.  Every admission counts as a bypass of each
+// older request still queued, which bounds how long a long request can be
+// overtaken; once one is past the bound and does not fit, nothing else is
+// admitted until it does.  Returns true if any request changed state.
 bool admit(bz_server* s) {
+  if (int(s->inflight.size()) >= s->d.max_inflight) return false;
   bool progress = false;
-  bool blocked = false;  // an earlier request ran out of bypasses
-  for (size_t qi = 0; qi < s->queue.size() && !blocked;) {
-    if (int(s->inflight.size()) >= s->d.max_inflight) return progress;
-    const uint64_t id = s->queue[qi];
-    Req& q = s->reqs[id];
+  struct Cand {
+    size_t pos;
+    bool urgent;
+    double work;
+  };
+  std::vector<Cand> cand;
+  const size_t window = std::min(s->queue.size(), kAdmitWindow);
+  std::vector<char> gone(window, 0);  // admitted or failed in this round
+  for (size_t qi = 0; qi < window; ++qi) {
+    Req& q = s->reqs[s->queue[qi]];
     CachedPlan* cp = q.cp ? q.cp : find_plan(s, q);
     q.cp = cp;
-    if (cp->state == kPlanBuilding) {  // waits for the builder, passed by the others
-      ++qi;
-      continue;
-    }
+    if (cp->state == kPlanBuilding) continue;  // waits for the builder, passed by the others
     if (cp->state == kPlanFailed) {
       finish(s, q, BZ_REQ_FAILED, cp->err);
-      s->queue.erase(s->queue.begin() + long(qi));
+      gone[qi] = 1;
       progress = true;
       continue;
     }
+    const double work = double(std::max(q.r.ncells, 1)) * double(cp->plan->npts) * double(cp->plan->m1);
+    cand.push_back({qi, q.bypassed > kMaxBypass, work});
+  }
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    if (a.urgent != b.urgent) return a.urgent;
+    if (a.urgent) return a.pos < b.pos;
+    return a.work < b.work;
+  });
+  std::vector<size_t> admitted;
+  for (const Cand& c : cand) {
+    if (int(s->inflight.size()) >= s->d.max_inflight) break;
+    const uint64_t id = s->queue[c.pos];
+    Req& q = s->reqs[id];
+    CachedPlan* cp = q.cp;
     const bz_plan* p = cp->plan;
     const size_t ws = p->ws_fixed + p->ws_per_cell * size_t(std::max(1, std::min(q.r.ncells, q.slice)));
     if (bz::align256(ws) + bz::align256(cp->tables_bytes) > s->arena.bytes) {  // can never fit
       finish(s, q, BZ_REQ_FAILED, BZ_ERR_NOMEM);
-      s->queue.erase(s->queue.begin() + long(qi));
+      gone[c.pos] = 1;
       progress = true;
       continue;
+    }
+    // headroom: a large workspace is not admitted ahead of its turn if it would
+    // leave less than an eighth of the arena free, so that short requests
+    // still find room while large ones run
+    if (!c.urgent && !s->inflight.empty() && bz::align256(ws) > s->arena.bytes / 16) {
+      const size_t need = bz::align256(ws) + (cp->resident ? 0 : bz::align256(cp->tables_bytes));
+      if (s->arena.used + need + s->arena.bytes / 8 > s->arena.bytes) continue;
     }
     size_t off = 0;
     bz_status perr = BZ_OK;
     if (!place(s, cp, ws, &off, &perr)) {
       if (perr != BZ_OK) {  // device error while uploading the tables
         finish(s, q, BZ_REQ_FAILED, perr);
-        s->queue.erase(s->queue.begin() + long(qi));
+        gone[c.pos] = 1;
         progress = true;
         continue;
       }
-      // no room while others run: wait for them (tables or workspace)
-      q.bypassed += 1;
-      if (q.bypassed > kMaxBypass) blocked = true;
-      ++qi;
+      if (c.urgent) break;  // no room while others run: the space that frees goes to it
       continue;
     }
     hipEvent_t ev = take_event(s);
-    s->queue.erase(s->queue.begin() + long(qi));
+    gone[c.pos] = 1;
     progress = true;
     if (!ev) {
       s->arena.release(off, ws);
@@ -580,8 +630,20 @@ bool admit(bz_server* s) {
     cp->inflight += 1;
     cp->last_use = q.t_admit;
     s->inflight.push_back(id);
+    admitted.push_back(c.pos);
   }
-  return progress;
+  if (!progress) return false;
+  // bypass counts of the requests still queued, then drop the others from the queue
+  for (size_t qi = 0; qi < window; ++qi) {
+    if (gone[qi]) continue;
+    for (size_t a : admitted)
+      if (a > qi) s->reqs[s->queue[qi]].bypassed += 1;
+  }
+  std::deque<uint64_t> rest;
+  for (size_t qi = 0; qi < s->queue.size(); ++qi)
+    if (qi >= window || !gone[qi]) rest.push_back(s->queue[qi]);
+  s->queue.swap(rest);
+  return true;
 }
 
 void scheduler(bz_server* s) {

@@ -142,8 +142,8 @@ def test_admission_bounded_by_arena():
 def test_failed_requests_are_isolated():
     import paper_2505_03360_amd as bz
     print("case serve failures", flush=True)
-    # an arena of 128 MB: one 4096-cell slice of an N = 16 request needs ~200 MB of workspace
-    srv = bz.Server(arena_bytes=128 << 20, max_inflight=4, n_streams=2)
+    # an arena of 48 MB: one 2048-cell slice of an N = 16 request needs ~100 MB of workspace
+    srv = bz.Server(arena_bytes=48 << 20, max_inflight=4, n_streams=2)
     f = inputs(16, 4, 8)
     good = torch.empty((4, 16, 16, 16), dtype=torch.float64, device="cuda")
     bad_n = bz.make_plan_desc(n=20, L=8.0, m=8, dir_kind=bz.BZ_DIRS_SPIRAL)
@@ -291,4 +291,36 @@ def test_sliced_requests_match_direct_slices():
     for qq in outs:
         assert torch.equal(qq, direct)
     OracleCells().check("sliced", f[:c], q, 37)
+    srv.close()
+
+
+def test_admission_prefers_short_requests_with_bounded_bypass():
+    """One in-flight slot.  While a long request runs, a second long request
+    and then twelve short ones queue: admission takes the least work first, so
+    short requests pass the queued long one, but at most nine of them (a
+    request passed over more than eight times goes first).  Every result
+    equals the same request served alone."""
+    import paper_2505_03360_amd as bz
+    print("case serve admission order", flush=True)
+    n, big, small = 48, 2048, 16
+    pd = plan(bz, n)
+    srv = bz.Server(arena_bytes=16 << 30, max_inflight=1, n_streams=1)
+    f = inputs(n, 64, 61).repeat(big // 64, 1, 1, 1).contiguous()
+    ref = {}
+    for c in (big, small):  # builds both plans (request sizes map to plan classes)
+        ref[c] = torch.empty((c, n, n, n), dtype=torch.float64, device="cuda")
+        assert wait(srv, srv.submit(f[:c], ref[c], pd)).state == bz.BZ_REQ_DONE
+    qa, qb = (torch.empty((big, n, n, n), dtype=torch.float64, device="cuda") for _ in range(2))
+    qs = [torch.empty((small, n, n, n), dtype=torch.float64, device="cuda") for _ in range(12)]
+    ta = srv.submit(f, qa, pd)
+    tb = srv.submit(f, qb, pd)
+    ts = [srv.submit(f[:small], q, pd) for q in qs]
+    ra, rb = wait(srv, ta), wait(srv, tb)
+    rs = [wait(srv, t) for t in ts]
+    assert all(r.state == bz.BZ_REQ_DONE for r in [ra, rb] + rs)
+    before_b = sum(r.t_admit_ns < rb.t_admit_ns for r in rs)
+    assert 1 <= before_b <= 9, before_b
+    assert torch.equal(qa, ref[big]) and torch.equal(qb, ref[big])
+    for q in qs:
+        assert torch.equal(q, ref[small])
     srv.close()
