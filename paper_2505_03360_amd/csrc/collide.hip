@@ -946,6 +946,16 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
     static_assert(sizeof(double) * N * N * SP <= sizeof(cx<float>) * (N * N + N - 1) * AB, "a slice fits the LDS");
     double* st = reinterpret_cast<double*>(lds);
     bool bad = false;
+    // IMEX: the two Maxwellians as per-axis Gaussian tables after the staging
+    // area ([mw][axis][j], 6 N doubles; written before the first slice's
+    // barrier, read after it)
+    [[maybe_unused]] double* gt = st + N * N * SP;
+    if constexpr (IMEX) {
+      static_assert(sizeof(double) * (N * N * SP + 6 * N) <= sizeof(cx<float>) * (N * N + N - 1) * AB,
+                    "the Gaussian tables fit beside a slice");
+      const double* par = a.im.par + size_t(cell) * bzk::kImexPar;
+      if (t < 6 * N) gt[t] = bzk::axis_gaussian(par, t / (3 * N), (t / N) % 3, t % N, N, a.dv);
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const double v3 = (s * W + tl - N / 2) * a.dv;
@@ -964,8 +974,11 @@ __global__ __launch_bounds__(N * N / S, (fused_min_waves<N, S>())) void k_collid
         double ov = st[jj * SP + jw];
         if constexpr (IMEX) {
           const size_t fe = size_t(row) * N * N * N + e;
-          ov = bzk::imex_point(a.im.par + size_t(cell) * bzk::kImexPar, ov, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
-                               (jj / N - N / 2) * a.dv, (jj % N - N / 2) * a.dv, (s * W + jw - N / 2) * a.dv);
+          const double* par = a.im.par + size_t(cell) * bzk::kImexPar;
+          const int j1 = jj / N, j2 = jj % N, j3 = s * W + jw;
+          const double m0 = par[0] * gt[j1] * gt[N + j2] * gt[2 * N + j3];
+          const double m1 = par[5] * gt[3 * N + j1] * gt[4 * N + j2] * gt[5 * N + j3];
+          ov = bzk::imex_combine(par[10], ov, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt, m0, m1);
         }
         q[e] = ov;
         bad |= !isfinite(ov);
@@ -1060,6 +1073,13 @@ __global__ __launch_bounds__(kProjThreads) void k_project(ProjArgs a) {
     return a.C * s;
   };
   const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
+  // IMEX: the two Maxwellians as per-axis Gaussian tables [mw][axis][j]
+  __shared__ double gt[6 * N];
+  const double* par = a.im.par + size_t(c) * bzk::kImexPar;
+  if (a.imex) {
+    if (t < 6 * N) gt[t] = bzk::axis_gaussian(par, t / (3 * N), (t / N) % 3, t % N, N, a.dv);
+    __syncthreads();
+  }
   double lam[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (a.project) {
     __shared__ double red[5 * (kProjWaves + 1)];
@@ -1085,7 +1105,10 @@ __global__ __launch_bounds__(kProjThreads) void k_project(ProjArgs a) {
     if (a.project) v -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
     if (a.imex) {
       const size_t fe = frow * N3 + j;
-      v = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, v, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt, v1, v2, v3);
+      const int j1 = j / (N * N), j2 = (j / N) % N, j3 = j % N;
+      const double m0 = par[0] * gt[j1] * gt[N + j2] * gt[2 * N + j3];
+      const double m1 = par[5] * gt[3 * N + j1] * gt[4 * N + j2] * gt[5 * N + j3];
+      v = bzk::imex_combine(par[10], v, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt, m0, m1);
     }
     if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * N3 + j] = v;
     else static_cast<float*>(a.q)[row * N3 + j] = float(v);
@@ -1129,6 +1152,11 @@ __global__ __launch_bounds__(kProjThreads) void k_project_pm(ProjArgs a) {
     proj_lambda(a, m, lam);
   }
   const double eps_c = a.imex ? (a.im.eps_cells ? a.im.eps_cells[frow] : a.im.eps) : 0.0;
+  // IMEX: the two Maxwellians as per-axis Gaussian tables [mw][axis][j]
+  // (read after the first tile's barrier)
+  __shared__ double gt[6 * N];
+  const double* par = a.im.par + size_t(c) * bzk::kImexPar;
+  if (a.imex && t < 6 * N) gt[t] = bzk::axis_gaussian(par, t / (3 * N), (t / N) % 3, t % N, N, a.dv);
   bool bad = false;
   for (int J0 = 0; J0 < N2; J0 += TC) {
     __syncthreads();  // the previous tile has been written out
@@ -1147,8 +1175,9 @@ __global__ __launch_bounds__(kProjThreads) void k_project_pm(ProjArgs a) {
       if (a.project) qv -= lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3);
       if (a.imex) {
         const size_t fe = frow * N3 + j;
-        qv = bzk::imex_point(a.im.par + size_t(c) * bzk::kImexPar, qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt,
-                             v1, v2, v3);
+        const double m0 = par[0] * gt[j1] * gt[N + j2] * gt[2 * N + j3];
+        const double m1 = par[5] * gt[3 * N + j1] * gt[4 * N + j2] * gt[5 * N + j3];
+        qv = bzk::imex_combine(par[10], qv, a.im.f[fe], a.im.tr[fe], eps_c, a.im.dt, m0, m1);
       }
       if (a.imex || a.project || !a.q_fp32) static_cast<double*>(a.q)[row * N3 + j] = qv;
       else static_cast<float*>(a.q)[row * N3 + j] = float(qv);

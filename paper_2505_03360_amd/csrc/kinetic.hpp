@@ -1,7 +1,7 @@
 // Per-cell kinetic quantities shared by the IMEX kernels: the Maxwellians of
-// the penalised update (Sec. 4.4, eq. (4.24)) are evaluated pointwise in the
-// epilogues of the collision kernels from parameters one reduction kernel
-// computes per cell.
+// the penalised update (Sec. 4.4, eq. (4.24)) are evaluated in the epilogues
+// of the collision and projection kernels, as products of per-axis Gaussians,
+// from parameters one reduction kernel computes per cell.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,17 +23,22 @@ struct ImexDev {
   double dt;
 };
 
-// f^{n+1} at one velocity node (eq. (4.24) with P(h) = beta (M[h] - h)):
+// f^{n+1} at one velocity node from the Maxwellians m0 = M^n, m1 = M^{n+1}
+// there (eq. (4.24) with P(h) = beta (M[h] - h)):
 //   (eps (f - dt tr) + dt (Q - beta (M^n - f)) + beta dt M^{n+1}) / (eps + beta dt)
-__device__ __forceinline__ double imex_point(const double* par, double q, double f, double tr, double eps,
-                                             double dt, double v1, double v2, double v3) {
-  const double d01 = v1 - par[1], d02 = v2 - par[2], d03 = v3 - par[3];
-  const double d11 = v1 - par[6], d12 = v2 - par[7], d13 = v3 - par[8];
-  const double m0 = par[0] * exp(-(d01 * d01 + d02 * d02 + d03 * d03) * par[4]);
-  const double m1 = par[5] * exp(-(d11 * d11 + d12 * d12 + d13 * d13) * par[9]);
-  const double beta = par[10];
+__device__ __forceinline__ double imex_combine(double beta, double q, double f, double tr, double eps, double dt,
+                                               double m0, double m1) {
   const double den = eps + beta * dt;
   return (eps * (f - dt * tr) + dt * (q - beta * (m0 - f)) + beta * dt * m1) / den;
+}
+
+// A Maxwellian on the grid is a product of one Gaussian per axis:
+// exp(-|v - u|^2 / 2T) = prod_a exp(-(v_a - u_a)^2 / 2T).  Table entry
+// [mw][axis][j] = exp(-(v_j - u_axis)^2 / 2T) of Maxwellian mw (0: M^n, 1:
+// M^{n+1}), v_j = (j - n/2) dv; 6 n doubles per cell.
+__device__ __forceinline__ double axis_gaussian(const double* par, int mw, int axis, int j, int n, double dv) {
+  const double d = (j - n / 2) * dv - par[5 * mw + 1 + axis];
+  return exp(-d * d * par[5 * mw + 4]);
 }
 
 }  // namespace bzk
