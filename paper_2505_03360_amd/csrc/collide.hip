@@ -675,7 +675,7 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   static_assert(wave_planes || (T % 64 == 0 && S == 1), "planes that straddle waves need whole waves, one slice");
   const int tk = t % N, tj = t / N;
   const cx<float>* mp = a.mult + size_t(p) * N * N * N;
-  const float wp = a.w[p];
+  [[maybe_unused]] const float wp = LOSS ? a.w[p] : 0.0f;
   // stage A: each pencil is loaded in two halves (bounded registers in
   // flight), transformed, and its slice-0 outputs go to LDS at once; the
   // other slices stay in registers until their turn.
@@ -714,10 +714,9 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
     }
     bzk::fft<N, 1>(u);
     bzk::fft<N, 1>(v);
-    auto out_b = [&](int j) -> cx<float> {
-      if (row0) return cx<float>{0.0f, 0.0f};
-      return cx<float>{u[j].x + v[j].y, v[j].x - u[j].y};
-    };
+    // row 0's threads write their mirror values into row N/2 (where the gain
+    // multipliers vanish), which stage B then reads as zeros
+    auto out_b = [&](int j) -> cx<float> { return cx<float>{u[j].x + v[j].y, v[j].x - u[j].y}; };
     lds_barrier();  // LDS free: every wave's previous stage C has read it
 #pragma unroll
     for (int j = 0; j < W; ++j) {
@@ -807,7 +806,8 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
     for (int r = 0; r < N; ++r) {
       const int k2 = bzk::first_stage_order<N>(r);
-      rb[k2] = lds[(k2 * N + tk) * AB + tj];
+      if (S == 2 && !LOSS && k2 == N / 2) rb[k2] = cx<float>{0.0f, 0.0f};  // see stage A
+      else rb[k2] = lds[(k2 * N + tk) * AB + tj];
     }
     bzk::fft<N, 1>(rb);
     // B -> C inside the wave: the wave has read every slot of its planes, and
@@ -834,8 +834,9 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
 #pragma unroll
       for (int j1 = 0; j1 < N; ++j1) acc[s][j1] -= (wp * fp[j1 * T] - rc[j1].y) * rc[j1].x;
     } else {
+      // the direction's weight is in its multipliers (sqrt|w| on each part)
 #pragma unroll
-      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += wp * rc[j1].x * rc[j1].y;
+      for (int j1 = 0; j1 < N; ++j1) acc[s][j1] += rc[j1].x * rc[j1].y;
     }
   }
 }

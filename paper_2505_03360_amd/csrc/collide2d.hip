@@ -159,8 +159,9 @@ __global__ __launch_bounds__(64, 2) void k_collide2d(Args2D a) {
       if (a.f_fp32) loss(opaque_global(static_cast<const float*>(a.f) + fbase + r));
       else loss(opaque_global(static_cast<const double*>(a.f) + fbase + r));
     } else {
+      // the angle's weight is in its multipliers (sqrt|w| on each part)
 #pragma unroll
-      for (int j1 = 0; j1 < N; ++j1) acc[j1] += wp * x[j1].x * x[j1].y;
+      for (int j1 = 0; j1 < N; ++j1) acc[j1] += x[j1].x * x[j1].y;
     }
   }
   const long orow = a.scatter ? row : long(cell);

@@ -581,10 +581,20 @@ void fill_tables_host(const bz_plan* p, unsigned char* host) {
   std::memset(host, 0, p->tables_bytes);
   const size_t entries = size_t(p->m1) * n3;
   if (p->fp32) {
+    // the fused kernels (three and two velocity dimensions) take a gain
+    // direction's weight in its multipliers: sqrt|w| on the real part and
+    // sign(w) sqrt|w| on the imaginary one, so that Re Y Im Y carries w
+    const bool weighted = p->transform == BZ_XF_FUSED;
     float* m = reinterpret_cast<float*>(host);
     for (size_t e = 0; e < entries; ++e) {
+      const int pass = int(e / n3);
       double re, im;
-      device_multiplier(p, int(e / n3), e % n3, re, im);
+      device_multiplier(p, pass, e % n3, re, im);
+      if (weighted && pass < p->m) {
+        const double w = p->wext[pass], sw = std::sqrt(std::fabs(w));
+        re *= sw;
+        im *= w < 0.0 ? -sw : sw;
+      }
       m[2 * e] = float(re);
       m[2 * e + 1] = float(im);
     }
@@ -608,8 +618,17 @@ void fill_tables_host(const bz_plan* p, unsigned char* host) {
             }
     }
   } else {
+    const bool weighted = p->transform == BZ_XF_FUSED;  // two velocity dimensions: as above
     double* m = reinterpret_cast<double*>(host);
-    for (size_t e = 0; e < entries; ++e) device_multiplier(p, int(e / n3), e % n3, m[2 * e], m[2 * e + 1]);
+    for (size_t e = 0; e < entries; ++e) {
+      const int pass = int(e / n3);
+      device_multiplier(p, pass, e % n3, m[2 * e], m[2 * e + 1]);
+      if (weighted && pass < p->m) {
+        const double w = p->wext[pass], sw = std::sqrt(std::fabs(w));
+        m[2 * e] *= sw;
+        m[2 * e + 1] *= w < 0.0 ? -sw : sw;
+      }
+    }
     std::memcpy(host + p->table_w_off, p->wext.data(), size_t(p->m1) * 8);
   }
 }
