@@ -480,14 +480,18 @@ bz_status bz_mask_sync(const int32_t* counts, void* stream);
  * simulation produces a request with its own grid size and cell count).
  *
  * The server carves plan tables and per-request workspaces out of one
- * caller-owned device arena; it never allocates device memory.  Requests are
- * admitted in arrival order as soon as their workspace fits in the arena and
- * an in-flight slot is free (a request that does not fit may be passed by at
- * most 8 later ones); admitted requests run on n_streams streams, so their
- * work overlaps on the device, and a request larger than the slice size runs
- * as consecutive slices, each launched when the previous one has finished on
- * the stream with the least estimated work queued (cells x grid points x
- * passes), so long requests interleave with short ones.
+ * caller-owned device arena; it never allocates device memory.  Queued
+ * requests are admitted, the one with the least estimated work (cells x grid
+ * points x passes) first, as soon as their workspace fits in the arena and an
+ * in-flight slot is free; a request passed over by more than 8 later ones goes
+ * first, and a workspace above a sixteenth of the arena is admitted ahead of
+ * that turn only if an eighth of the arena stays free.  Admitted requests run
+ * on n_streams streams, one slice per stream at a time, so their work overlaps
+ * on the device; a request larger than the slice size runs as consecutive
+ * slices, and a free stream takes the next slice of the admitted request with
+ * the least work left, so long requests interleave with short ones.  With two
+ * or more streams, stream 0 takes only short slices (at most 3 * 2^28 grid
+ * points x passes), so a short request never waits for a long slice.
  * The strategy of a request's plan is that of its slice size.  Plans are cached by descriptor (max_cells is
  * ignored): the host plan is built on a builder thread the first time an
  * operator is requested (meanwhile its requests wait and the others go
