@@ -491,7 +491,8 @@ bz_status bz_mask_sync(const int32_t* counts, void* stream);
  * slices, and a free stream takes the next slice of the admitted request with
  * the least work left, so long requests interleave with short ones.  With two
  * or more streams, stream 0 takes only short slices (at most 3 * 2^28 grid
- * points x passes), so a short request never waits for a long slice.
+ * points x passes), so a short request never waits for a long slice; a
+ * request passed over by more than 32 slice launches goes first.
  * The strategy of a request's plan is that of its slice size.  Plans are cached by descriptor (max_cells is
  * ignored): the host plan is built on a builder thread the first time an
  * operator is requested (meanwhile its requests wait and the others go

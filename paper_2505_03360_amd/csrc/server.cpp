@@ -180,6 +180,7 @@ struct Req {
   int done_cells = 0;  // cells whose slice has been launched
   int stream = -1;     // stream of the slice in flight (-1: admitted, waiting for its next slice)
   double work = 0.0;   // estimated work of the slice in flight
+  int dispatch_bypassed = 0;  // slices of other requests launched while this one waited
 };
 
 // Slices queued per stream at most: the server, not the streams' FIFO order,
@@ -442,28 +443,20 @@ double next_slice_work(const Req& q) {
   return double(cnt) * double(q.cp->plan->npts) * double(q.cp->plan->m1);
 }
 
-// Launch slices while a stream has room (fewer than kStreamDepth queued): the
-// waiting request with the least work left goes first, on the stream with the
-// fewest (then the lightest) slices queued, so short requests overtake long
-// ones at slice boundaries; long slices keep off stream 0.
+// Launch slices while a stream has room (fewer than kStreamDepth queued): of
+// the waiting requests that can launch now, the one with the least work left
+// goes first, on the stream with the fewest (then the lightest) slices queued,
+// so short requests overtake long ones at slice boundaries; long slices keep
+// off stream 0.  A request passed over by more than kMaxDispatchBypass
+// launches goes first (the one passed over most), which bounds how long a long
+// request can be held back.
+constexpr int kMaxDispatchBypass = 32;
+
 void dispatch(bz_server* s) {
-  for (;;) {
-    size_t best = s->inflight.size();
-    double best_work = 0.0;
-    for (size_t i = 0; i < s->inflight.size(); ++i) {
-      const Req& q = s->reqs[s->inflight[i]];
-      if (q.stream >= 0) continue;
-      const double w = remaining_work(q);
-      if (best == s->inflight.size() || w < best_work) {
-        best = i;
-        best_work = w;
-      }
-    }
-    if (best == s->inflight.size()) return;
-    Req& q = s->reqs[s->inflight[best]];
-    const bool long_slice = s->streams.size() > 1 && next_slice_work(q) > kShortWork;
+  const bool split = s->streams.size() > 1;
+  auto free_stream = [s](int lo) {
     int st_i = -1;
-    for (int i = long_slice ? 1 : 0; i < int(s->streams.size()); ++i) {
+    for (int i = lo; i < int(s->streams.size()); ++i) {
       const size_t a = size_t(i);
       if (s->stream_depth[a] >= kStreamDepth) continue;
       if (st_i < 0) {
@@ -475,7 +468,36 @@ void dispatch(bz_server* s) {
           (s->stream_depth[a] == s->stream_depth[b] && s->stream_load[a] < s->stream_load[b]))
         st_i = i;
     }
-    if (st_i < 0) return;  // the waiting requests with less work go first once a stream frees
+    return st_i;
+  };
+  for (;;) {
+    const int any = free_stream(0);
+    if (any < 0) return;
+    const int any_long = split ? free_stream(1) : any;
+    size_t best = s->inflight.size();
+    double best_key = 0.0;
+    bool best_urgent = false, best_long = false;
+    for (size_t i = 0; i < s->inflight.size(); ++i) {
+      const Req& q = s->reqs[s->inflight[i]];
+      if (q.stream >= 0) continue;
+      const bool lng = split && next_slice_work(q) > kShortWork;
+      if (lng && any_long < 0) continue;  // only stream 0 is free
+      const bool urgent = q.dispatch_bypassed > kMaxDispatchBypass;
+      const double key = urgent ? -double(q.dispatch_bypassed) : remaining_work(q);
+      if (best == s->inflight.size() || (urgent && !best_urgent) || (urgent == best_urgent && key < best_key)) {
+        best = i;
+        best_key = key;
+        best_urgent = urgent;
+        best_long = lng;
+      }
+    }
+    if (best == s->inflight.size()) return;
+    const int st_i = best_long ? any_long : any;
+    const uint64_t id = s->inflight[best];
+    for (uint64_t o : s->inflight)
+      if (o != id && s->reqs[o].stream < 0) s->reqs[o].dispatch_bypassed += 1;
+    Req& q = s->reqs[id];
+    q.dispatch_bypassed = 0;
     const bz_status lst = launch_slice(s, q, st_i);
     if (lst != BZ_OK) {
       for (auto x : s->streams) (void)hipStreamSynchronize(x);  // nothing of a failed launch stays in flight
