@@ -692,7 +692,8 @@ def main():
     ap.add_argument("--sweep-m", type=int, nargs="*", default=[32, 64])
     ap.add_argument("--sweep-gamma", type=float, nargs="*", default=[0.0, 0.5, 1.0])
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
+                    help="also run a plain 256 MiB device copy (scale reference for HBM byte counters) "
+                         "and time a 1 GiB one (device_copy in the JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the collision evaluation of a cell batch runs on a "
@@ -754,12 +755,28 @@ def main():
     n_cancel = int((floor > rn).sum())
     batch_rel = float(torch.linalg.vector_norm(dq) / torch.linalg.vector_norm(out64))
 
+    device_copy = None
     if args.copy_calibration:
+        # the 256 MiB copies are the reference of the traffic counters; a
+        # timed 1 GiB device copy gives the read+write HBM rate a plain
+        # streaming kernel reaches on this device
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(10):
+            dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / 10 * 1e-3
+        device_copy = {"bytes": 2 * src.numel() * 4, "ms": t * 1e3, "TB_s": 2 * src.numel() * 4 / t / 1e12}
         del src, dst
 
     total_flops, kern_flops = algorithmic_flops(N, M)
@@ -800,6 +817,8 @@ def main():
                                            "cells against the FP64 GPU path; cancellation cells: the floor binds"},
         "algorithmic_tflops_whole_step": total_flops * value / 1e12,
     }
+    if device_copy is not None:
+        rec["device_copy"] = device_copy
     rec["single_cell"] = single_cell_latency()
     rec["kinetic"] = kinetic_run(col, f, max(2, args.steps // 2))
     rec["dealiased"] = dealias_run(f, out, max(2, args.steps // 4))
