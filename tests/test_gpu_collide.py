@@ -320,3 +320,28 @@ def test_maximum_request_size_sampled(n):
         assert err <= 1e-5
     assert torch.equal(q[0], q[16])  # identical inputs give identical outputs anywhere in the batch
     col.close()
+
+
+@pytest.mark.parametrize("n,precision,tol,transform", [(16, 1, 1e-5, 1), (32, 1, 1e-5, 1), (16, 0, 1e-12, 2)])
+def test_explicit_rule_with_a_negative_weight(n, precision, tol, transform):
+    """An explicit direction rule (the 8-point spiral's directions) with
+    uneven weights, one of them negative, summing to 2 pi: the fused FP32
+    kernels take each direction's weight inside its multipliers (sqrt|w| on
+    the real part, sign(w) sqrt|w| on the imaginary one) and the plain FP64
+    path multiplies by it; both against the oracle with the same rule."""
+    import paper_2505_03360_amd as bz
+    from oracle import directions
+    label("explicit rule, negative weight", n, precision, transform)
+    d, _ = directions.spiral(8)
+    c = np.array([1.8, -0.5, 1.0, 1.2, 0.5, 1.5, 1.0, 0.6])
+    w = c / c.sum() * 2 * np.pi
+    f = gen.bimaxwellian_batch(3, n, 8.0, seed=41)
+    col = bz.Collider(n, 3, L=8.0, precision=precision, dirs=d, weights=w, transform=transform)
+    assert col.transform == transform
+    q = run(col, f)
+    plan = spectral.Plan(n, 8.0, spectral.default_R(8.0), 1.0, 4.0, d, w)
+    ref, loss = oracle_cells(f, plan)
+    err = cell_errors(q, ref, loss)
+    assert err.max() <= tol, err
+    for i in range(3):
+        assert spectral.moment_drift(q[i], n, 8.0) <= 1e-12
