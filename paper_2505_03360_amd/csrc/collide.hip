@@ -705,6 +705,10 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+          if (k3 == N / 2) {  // the gain multipliers vanish on the Nyquist plane: nothing to load
+            u[k3] = v[k3] = cx<float>{0.0f, 0.0f};
+            continue;
+          }
           const cx<float> F = fb[k3 * N], Mu = mb[k3 * N];
           u[k3] = {Mu.x * F.x, Mu.x * F.y};
           v[k3] = {Mu.y * F.x, Mu.y * F.y};
