@@ -767,6 +767,10 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
+          if (!LOSS && k3 == N / 2) {  // the gain multipliers vanish on the Nyquist plane
+            x[k3] = cx<float>{0.0f, 0.0f};
+            continue;
+          }
           const cx<float> F = fb[k3 * N];
           const cx<float> M = mb[k3 * N];
           x[k3] = {M.x * F.x - M.y * F.y, M.x * F.y + M.y * F.x};
