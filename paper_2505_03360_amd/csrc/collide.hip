@@ -676,9 +676,10 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
   const int tk = t % N, tj = t / N;
   const cx<float>* mp = a.mult + size_t(p) * N * N * N;
   [[maybe_unused]] const float wp = LOSS ? a.w[p] : 0.0f;
-  // stage A: each pencil is loaded in two halves (bounded registers in
-  // flight), transformed, and its slice-0 outputs go to LDS at once; the
-  // other slices stay in registers until their turn.
+  // stage A: each pencil is loaded (the paired gain pencils in one batch of
+  // loads, whose products start as the first loads land; the unpaired ones in
+  // two halves, which measured faster there), transformed, and its slice-0
+  // outputs go to LDS at once; the other slices stay in registers until their turn.
   // The loads and transforms of stage A touch registers only: a wave runs
   // them while other waves are still in the previous pass's stage C, and
   // waits (LDS free) only before its first LDS write.
@@ -702,19 +703,16 @@ __device__ __forceinline__ void fused_pass(const FusedArgs& a, cx<float>* lds, c
       const gptr<cx<float>> fb = opaque_global(fhc + off);
       const gptr<cx<float>> mb = opaque_global(mp + off);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int k3 = h * (N / 2); k3 < (h + 1) * (N / 2); ++k3) {
-          if (k3 == N / 2) {  // the gain multipliers vanish on the Nyquist plane: nothing to load
-            u[k3] = v[k3] = cx<float>{0.0f, 0.0f};
-            continue;
-          }
-          const cx<float> F = fb[k3 * N], Mu = mb[k3 * N];
-          u[k3] = {Mu.x * F.x, Mu.x * F.y};
-          v[k3] = {Mu.y * F.x, Mu.y * F.y};
+      for (int k3 = 0; k3 < N; ++k3) {
+        if (k3 == N / 2) {  // the gain multipliers vanish on the Nyquist plane: nothing to load
+          u[k3] = v[k3] = cx<float>{0.0f, 0.0f};
+          continue;
         }
-        __builtin_amdgcn_sched_barrier(0);
+        const cx<float> F = fb[k3 * N], Mu = mb[k3 * N];
+        u[k3] = {Mu.x * F.x, Mu.x * F.y};
+        v[k3] = {Mu.y * F.x, Mu.y * F.y};
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
     bzk::fft<N, 1>(u);
     bzk::fft<N, 1>(v);
